@@ -1,0 +1,207 @@
+"""ctypes wrapper of the CPU oracle (zsort_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg.  The product path never imports this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "zsort_oracle.c")
+_LIB = os.path.join(_HERE, "libzsort_oracle.so")
+
+GCC_CMD = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+
+
+def build() -> str:
+    """Compile the oracle (always recompiles)."""
+    subprocess.run(GCC_CMD, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, U64, I64, I32, D = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                               ctypes.c_int, ctypes.c_double)
+        L.zo_u256_to_double.argtypes = [P]
+        L.zo_u256_to_double.restype = D
+        L.zo_moments.argtypes = [P, U64, P]
+        L.zo_zstats.argtypes = [U64, P, P, I32, I32, D, U64, P]
+        L.zo_zstats.restype = I32
+        L.zo_zbucket.argtypes = [U64, U64, D, D, D, I32]
+        L.zo_zbucket.restype = I32
+        L.zo_rshift.argtypes = [U64, I32]
+        L.zo_rshift.restype = I32
+        L.zo_rbucket.argtypes = [U64, U64, I32]
+        L.zo_rbucket.restype = I32
+        L.zo_mean_est.argtypes = [I32, D, D, D, D]
+        L.zo_mean_est.restype = D
+        L.zo_sort.argtypes = [P, P, I32, U64, P, P, I64, P, I64, P]
+        L.zo_sort.restype = I32
+        L.zo_level0.argtypes = [P, P, I32, U64, P, P, P, I64]
+        L.zo_level0.restype = I32
+        L.zo_sort_segmented.argtypes = [P, P, I32, U64, P, I64, P]
+        L.zo_sort_segmented.restype = I32
+        L.zo_brute_stable_sort.argtypes = [P, P, I32, U64]
+        L.zo_brute_stable_sort.restype = I32
+        L.zo_seg_rec_size.restype = I32
+        assert L.zo_seg_rec_size() == SEG_REC.itemsize
+        _lib = L
+    return _lib
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("max_zlevels", ctypes.c_int32), ("counting_range", ctypes.c_int32)]
+
+
+SEG_REC = np.dtype([
+    ("depth", np.int32), ("kind", np.int32), ("start", np.uint64), ("count", np.uint64),
+    ("o", np.uint64), ("M", np.uint64), ("s1", np.uint64, 2), ("s2", np.uint64, 4),
+    ("m", np.float64), ("sigma", np.float64), ("zmin", np.float64), ("A", np.float64),
+    ("B", np.float64), ("shift", np.int32), ("nonempty", np.int32), ("hist_off", np.int64),
+])
+
+KIND_IDENT, KIND_ZMAP, KIND_RMAP, KIND_COUNT = 1, 2, 3, 4
+
+
+def paper_params(n: int, alpha: float = 1.0, max_zlevels: int = 16) -> dict:
+    """Algorithm 1's settings: clusters = alpha*sqrt(n) (alpha = 1 in the
+    listing, 0.6 best in the sensitivity table), insertion sort at <= 96."""
+    return dict(k=max(2, int(math.floor(alpha * math.sqrt(max(n, 1))))), cutoff=96,
+                max_zlevels=max_zlevels, counting_range=0)
+
+
+def _params(k, cutoff, max_zlevels, counting_range=0):
+    return Params(int(k), int(cutoff), int(max_zlevels), int(counting_range))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _pw(payload):
+    if payload is None:
+        return 0
+    if payload.dtype.itemsize not in (4, 8):
+        raise ValueError("payload must be 4 or 8 bytes wide")
+    return payload.dtype.itemsize
+
+
+def u256_to_double(v: int) -> float:
+    w = np.array([(v >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+    return lib().zo_u256_to_double(w.ctypes.data)
+
+
+def moments(x: np.ndarray):
+    """(min, max, S1, S2) with S1, S2 about the minimum, as Python ints."""
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    out = np.zeros(8, dtype=np.uint64)
+    lib().zo_moments(x.ctypes.data, x.size, out.ctypes.data)
+    o = [int(v) for v in out]
+    s1 = o[2] | (o[3] << 64)
+    s2 = sum(v << (64 * i) for i, v in enumerate(o[4:8]))
+    return o[0], o[1], s1, s2
+
+
+def zstats(c: int, s1: int, s2: int, k: int, is_root: bool = True, e: float = 0.0,
+           o_rel: int = 0):
+    """(ok, m, var, sigma, zmin, A, B)"""
+    s1w = np.array([s1 & (2**64 - 1), s1 >> 64], dtype=np.uint64)
+    s2w = np.array([(s2 >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+    out = np.zeros(6, dtype=np.float64)
+    ok = lib().zo_zstats(c, s1w.ctypes.data, s2w.ctypes.data, k, int(is_root), e, o_rel,
+                         out.ctypes.data)
+    return (bool(ok),) + tuple(float(v) for v in out)
+
+
+def zbucket(x: int, o: int, m: float, A: float, B: float, k: int) -> int:
+    return lib().zo_zbucket(x, o, m, A, B, k)
+
+
+def rshift(R: int, k: int) -> int:
+    return lib().zo_rshift(R, k)
+
+
+def rbucket(x: int, o: int, shift: int) -> int:
+    return lib().zo_rbucket(x, o, shift)
+
+
+def mean_est(j: int, scale: float, zmin: float, sigma: float, m: float) -> float:
+    return lib().zo_mean_est(j, scale, zmin, sigma, m)
+
+
+def sort(keys: np.ndarray, payload=None, k=1024, cutoff=96, max_zlevels=8,
+         counting_range=0, trace=False, trace_cap=1 << 16, hist_cap=1 << 22):
+    """Returns (keys, payload, info) sorted copies; with trace=True also
+    (records, histograms)."""
+    x = np.array(keys, dtype=np.uint64, copy=True)
+    p = None if payload is None else np.array(payload, copy=True)
+    pw = _pw(p)
+    prm = _params(k, cutoff, max_zlevels, counting_range)
+    info = np.zeros(3, dtype=np.int64)
+    if trace:
+        tr = np.zeros(trace_cap, dtype=SEG_REC)
+        hist = np.zeros(hist_cap, dtype=np.uint32)
+        rc = lib().zo_sort(x.ctypes.data, _ptr(p), pw, x.size, ctypes.byref(prm),
+                           tr.ctypes.data, trace_cap, hist.ctypes.data, hist_cap,
+                           info.ctypes.data)
+    else:
+        rc = lib().zo_sort(x.ctypes.data, _ptr(p), pw, x.size, ctypes.byref(prm),
+                           None, 0, None, 0, info.ctypes.data)
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    if trace:
+        nrec = int(min(info[0], trace_cap))
+        return x, p, info, tr[:nrec], hist[: int(info[1])]
+    return x, p, info
+
+
+def level0(keys: np.ndarray, payload=None, k=1024, cutoff=96, max_zlevels=8):
+    """One distribution pass of the root: (cluster array keys, payload,
+    root record, histogram[k])."""
+    x = np.array(keys, dtype=np.uint64, copy=True)
+    p = None if payload is None else np.array(payload, copy=True)
+    prm = _params(k, cutoff, max_zlevels)
+    tr = np.zeros(1, dtype=SEG_REC)
+    hist = np.zeros(k, dtype=np.uint32)
+    rc = lib().zo_level0(x.ctypes.data, _ptr(p), _pw(p), x.size, ctypes.byref(prm),
+                         tr.ctypes.data, hist.ctypes.data, k)
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return x, p, tr[0], hist
+
+
+def sort_segmented(keys, offsets, payload=None, k=1024, cutoff=96, max_zlevels=8):
+    x = np.array(keys, dtype=np.uint64, copy=True)
+    p = None if payload is None else np.array(payload, copy=True)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    prm = _params(k, cutoff, max_zlevels)
+    rc = lib().zo_sort_segmented(x.ctypes.data, _ptr(p), _pw(p), x.size, off.ctypes.data,
+                                 off.size - 1, ctypes.byref(prm))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return x, p
+
+
+def brute_stable_sort(keys, payload=None):
+    x = np.array(keys, dtype=np.uint64, copy=True)
+    p = None if payload is None else np.array(payload, copy=True)
+    rc = lib().zo_brute_stable_sort(x.ctypes.data, _ptr(p), _pw(p), x.size)
+    if rc:
+        raise ValueError("bad arguments")
+    return x, p
