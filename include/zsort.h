@@ -1,0 +1,198 @@
+/*
+ * zsort.h -- C-ABI of the MI355X (gfx950) zSort library.
+ *
+ * The library sorts 64-bit unsigned keys, stably, carrying a 0-, 4- or 8-byte
+ * payload with each key, by the z-score distribution method of
+ * "zSort: Stable Distribution Sort using Z-Score Partitioning"
+ * (arXiv 2605.14419): Section III (problem statement: clusters with
+ * max(C_j) < min(C_j+1); stability; duplicate handling; the mapping function
+ * of Eq. (1) with its clip; the estimated mean of the recursive phase) and
+ * Algorithm 1 (moments, histogram, exclusive prefix, stable scatter,
+ * recursion, small-cluster sort).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named keys/payload/seg_offsets are DEVICE pointers owned by the
+ *     caller.  Sorting is in place: on return (after the stream has reached
+ *     the call) keys[0, n) is ascending as unsigned 64-bit integers and every
+ *     payload element sits beside the key it came with; keys that compare
+ *     equal keep their input order (the stable order, which makes the output
+ *     unique).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it and the call returns without waiting for the device, except that
+ *     the first call at a new problem size allocates the workspace
+ *     (hipMalloc, which synchronises the device).
+ *   - Limits: 1 <= n <= 2^31 - 1 keys per call (n <= 1 is a no-op that
+ *     returns ZSORT_OK).  Buffers must not overlap.
+ *   - Errors are returned as negative status codes; nothing throws across the
+ *     ABI and no caller memory is freed.  Capacity overruns detected on the
+ *     device are reported by zsort_get_last_stats (field device_error).
+ *   - Calls on one stream are serialised; calls on different streams use
+ *     different workspaces and may run concurrently.
+ */
+#ifndef ZSORT_H
+#define ZSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ZSORT_OK = 0,
+  ZSORT_EINVAL = -1,        /* bad argument (null pointer, size, config) */
+  ZSORT_ENOMEM = -2,        /* device allocation failed */
+  ZSORT_EHIP = -3,          /* a HIP runtime call failed (see zsort_last_hip_error) */
+  ZSORT_ECAPTURE = -4,      /* the call would allocate while its stream is being captured */
+  ZSORT_EUNSUPPORTED = -5,  /* configuration not built into this library */
+  ZSORT_EDEVICE = -6        /* a device-side limit was hit (only from synchronous calls) */
+};
+
+/*
+ * Tuning of the distribution.  k and cutoff change the recursion tree (and
+ * therefore the intermediate arrays) but never the output.
+ *   k            clusters per distribution pass, 16..4096.  The paper uses
+ *                k = sqrt(n) held constant across levels (Section III, choice
+ *                of k); here k is a constant "buckets per pass".  Default 1024.
+ *   cutoff       clusters of at most this many keys are finished by the local
+ *                (in-LDS) stable sort, 1..2048 (the paper's insertion-sort
+ *                threshold is 96).  Default 2048.
+ *   max_zlevels  depth at which the z-score map gives way to the exact range
+ *                map, 0..16 (0 = range map everywhere).  Default 8.
+ *   chunk        keys per work item of a pass, a multiple of 2048 in
+ *                [2048, 2^20].  Default 16384.
+ */
+typedef struct zsort_config {
+  int32_t k;
+  int32_t cutoff;
+  int32_t max_zlevels;
+  int32_t chunk;
+  int32_t reserved[4];
+} zsort_config;
+
+/* Fills cfg with the defaults above.  Returns ZSORT_OK or ZSORT_EINVAL (null). */
+int zsort_default_config(zsort_config* cfg);
+
+/*
+ * Stable sort of keys[0, n) with an optional u32 payload (payload may be
+ * NULL).  The default configuration is used.
+ */
+int zsort_stable(uint64_t* keys, uint32_t* payload, size_t n, void* stream);
+
+/* As zsort_stable with a u64 payload (may be NULL). */
+int zsort_stable_p64(uint64_t* keys, uint64_t* payload, size_t n, void* stream);
+
+/*
+ * General form: payload_bytes is 0 (payload ignored, may be NULL), 4 or 8;
+ * cfg may be NULL (defaults).
+ */
+int zsort_stable_ex(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                    const zsort_config* cfg, void* stream);
+
+/*
+ * Batched form: num_segments independent arrays laid end to end in keys[0, n);
+ * segment i is [seg_offsets[i], seg_offsets[i+1]).  seg_offsets is a DEVICE
+ * array of num_segments + 1 int64 with seg_offsets[0] = 0,
+ * seg_offsets[num_segments] = n and non-decreasing entries (empty segments
+ * allowed).  Each segment is sorted on its own, stably.  The offsets are
+ * checked on the device; if they are malformed nothing is moved and
+ * zsort_get_last_stats reports device_error bit 0x100.  payload_bytes is
+ * 0, 4 or 8; cfg may be NULL.  All segments go through one set of launches
+ * (the recursion levels of every segment run together).
+ */
+int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                           const int64_t* seg_offsets, int32_t num_segments,
+                           const zsort_config* cfg, void* stream);
+
+/* Device bytes of workspace a call of this shape needs (0 if invalid). */
+size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
+                             const zsort_config* cfg);
+
+/*
+ * Statistics of the last call on `stream` (synchronises that stream).
+ *   levels            number of recursion levels that held work
+ *   device_error      0, or bits: 1 segment list, 2 work list, 4 leaf list,
+ *                     8 look-back slots full, 16 look-back wait limit,
+ *                     0x100 malformed segment offsets
+ *   keys_per_level    keys distributed at each level
+ *   segs_per_level    subproblems distributed at each level
+ *   mkeys_per_level   keys whose moments were taken at each level
+ *   model_bytes       algorithmic HBM bytes of the executed pass structure:
+ *                     per level 8 B/key (moments) + 8 B/key (histogram) +
+ *                     2(8+P) B/key (scatter), plus 2(8+P) B/key for the
+ *                     final local sort / copy
+ */
+#define ZSORT_MAX_LEVELS 40
+typedef struct zsort_stats {
+  int32_t levels;
+  int32_t device_error;
+  uint32_t identical;
+  uint32_t range_mapped;
+  uint32_t leaf_groups;
+  int32_t payload_bytes;
+  uint64_t n;
+  uint64_t keys_per_level[ZSORT_MAX_LEVELS];
+  uint64_t mkeys_per_level[ZSORT_MAX_LEVELS];
+  uint32_t segs_per_level[ZSORT_MAX_LEVELS];
+  double model_bytes;
+} zsort_stats;
+
+int zsort_get_last_stats(void* stream, zsort_stats* out /* host */);
+
+/*
+ * Parity/debug entry: one distribution pass of the root (moments, statistics,
+ * histogram, scan, stable scatter), without recursion.  The resulting cluster
+ * array (Algorithm 1's single array separated by offsets) is copied to
+ * out_keys / out_payload (device, n elements; out_payload may be NULL when
+ * payload_bytes is 0).  keys/payload are left unchanged.  Requires
+ * n > cfg->cutoff.  Synchronous.
+ */
+int zsort_debug_level0(const uint64_t* keys, const void* payload, int payload_bytes, size_t n,
+                       const zsort_config* cfg, uint64_t* out_keys, void* out_payload,
+                       void* stream);
+
+/*
+ * Record of one subproblem larger than the cutoff, for level-by-level parity:
+ * depth, kind (1 identical keys, 2 z-score map, 3 range map), position and
+ * size, exact moments about the minimum (S1: 2 limbs, S2: 4 limbs,
+ * little-endian), the binary64 statistics of the map, the range-map shift,
+ * the number of non-empty clusters and the offset of its k cluster counts in
+ * the histogram output (-1 if not stored).
+ */
+typedef struct zsort_trace_rec {
+  int32_t depth;
+  int32_t kind;
+  uint64_t start, count;
+  uint64_t o, M;
+  uint64_t s1[2];
+  uint64_t s2[4];
+  double m, sigma, zmin, A, B;
+  int32_t shift;
+  int32_t nonempty;
+  int64_t hist_off;
+} zsort_trace_rec;
+
+/*
+ * zsort_stable_ex that also records every subproblem (host buffers; records
+ * in no particular order).  counts[0] = records produced (may exceed
+ * trace_cap), counts[1] = histogram words stored.  Synchronous; returns
+ * ZSORT_EDEVICE if a device-side limit was hit.
+ */
+int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                        const zsort_config* cfg, zsort_trace_rec* trace, int64_t trace_cap,
+                        uint32_t* hist, int64_t hist_cap, int64_t counts[2], void* stream);
+
+/* Frees every cached workspace (synchronises the device). */
+int zsort_release(void);
+
+/* Last hipError_t seen by the library (0 if none). */
+int zsort_last_hip_error(void);
+
+/* Static description of a status code. */
+const char* zsort_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZSORT_H */

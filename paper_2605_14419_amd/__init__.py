@@ -1,0 +1,230 @@
+"""Python binding of the zSort C-ABI (include/zsort.h).
+
+Argument marshalling only: every step of the sort runs in the HIP kernels of
+the in-tree library ``_lib/libzsort.so``.  PyTorch supplies device memory and
+streams.  There is no fallback: if the library has not been built the first
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libzsort.so")
+
+ZSORT_OK, ZSORT_EINVAL, ZSORT_ENOMEM, ZSORT_EHIP, ZSORT_ECAPTURE, ZSORT_EUNSUPPORTED, \
+    ZSORT_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+MAX_LEVELS = 40
+
+EXPORTED = [
+    "zsort_default_config", "zsort_stable", "zsort_stable_p64", "zsort_stable_ex",
+    "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
+    "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
+    "zsort_strerror",
+]
+
+
+class ZsortConfig(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("max_zlevels", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class ZsortStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("device_error", ctypes.c_int32),
+                ("identical", ctypes.c_uint32), ("range_mapped", ctypes.c_uint32),
+                ("leaf_groups", ctypes.c_uint32), ("payload_bytes", ctypes.c_int32),
+                ("n", ctypes.c_uint64),
+                ("keys_per_level", ctypes.c_uint64 * MAX_LEVELS),
+                ("mkeys_per_level", ctypes.c_uint64 * MAX_LEVELS),
+                ("segs_per_level", ctypes.c_uint32 * MAX_LEVELS),
+                ("model_bytes", ctypes.c_double)]
+
+
+TRACE_REC = np.dtype([
+    ("depth", np.int32), ("kind", np.int32), ("start", np.uint64), ("count", np.uint64),
+    ("o", np.uint64), ("M", np.uint64), ("s1", np.uint64, 2), ("s2", np.uint64, 4),
+    ("m", np.float64), ("sigma", np.float64), ("zmin", np.float64), ("A", np.float64),
+    ("B", np.float64), ("shift", np.int32), ("nonempty", np.int32), ("hist_off", np.int64),
+])
+
+
+class ZsortError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {code} ({strerror(code)}), hip error {last_hip_error()}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was never built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"zsort HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, Z, I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        L.zsort_default_config.argtypes = [P]
+        L.zsort_stable.argtypes = [P, P, Z, P]
+        L.zsort_stable_p64.argtypes = [P, P, Z, P]
+        L.zsort_stable_ex.argtypes = [P, P, I, Z, P, P]
+        L.zsort_stable_segmented.argtypes = [P, P, I, Z, P, ctypes.c_int32, P, P]
+        L.zsort_workspace_bytes.argtypes = [Z, I, ctypes.c_int32, P]
+        L.zsort_workspace_bytes.restype = Z
+        L.zsort_get_last_stats.argtypes = [P, P]
+        L.zsort_debug_level0.argtypes = [P, P, I, Z, P, P, P, P]
+        L.zsort_stable_traced.argtypes = [P, P, I, Z, P, P, ctypes.c_int64, P, ctypes.c_int64,
+                                          P, P]
+        L.zsort_strerror.argtypes = [I]
+        L.zsort_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().zsort_strerror(int(code)).decode()
+
+
+def last_hip_error() -> int:
+    return int(lib().zsort_last_hip_error())
+
+
+def _check(fn, rc):
+    if rc != ZSORT_OK:
+        raise ZsortError(fn, rc)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _keys_ptr(keys):
+    import torch
+    if not keys.is_cuda or keys.dtype not in (torch.int64, torch.uint64) or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous int64/uint64 CUDA tensor (read as u64)")
+    return ctypes.c_void_p(keys.data_ptr())
+
+
+def _pay(payload, n):
+    import torch
+    if payload is None:
+        return None, 0
+    if not payload.is_cuda or not payload.is_contiguous() or payload.numel() != n:
+        raise ValueError("payload must be a contiguous CUDA tensor with one element per key")
+    if payload.dtype in (torch.int32, torch.uint32):
+        return ctypes.c_void_p(payload.data_ptr()), 4
+    if payload.dtype in (torch.int64, torch.uint64):
+        return ctypes.c_void_p(payload.data_ptr()), 8
+    raise ValueError("payload dtype must be 4 or 8 bytes wide")
+
+
+def zsort_default_config(**overrides) -> ZsortConfig:
+    c = ZsortConfig()
+    _check("zsort_default_config", lib().zsort_default_config(ctypes.byref(c)))
+    for k, v in overrides.items():
+        setattr(c, k, int(v))
+    return c
+
+
+def _cfg(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, dict):
+        cfg = zsort_default_config(**cfg)
+    return ctypes.byref(cfg)
+
+
+def zsort_stable(keys, payload=None, stream=None):
+    """u32 payload (or None)."""
+    p, pw = _pay(payload, keys.numel())
+    if pw not in (0, 4):
+        raise ValueError("zsort_stable takes a 4-byte payload")
+    _check("zsort_stable", lib().zsort_stable(_keys_ptr(keys), p, keys.numel(), _stream(stream)))
+
+
+def zsort_stable_p64(keys, payload=None, stream=None):
+    """u64 payload (or None)."""
+    p, pw = _pay(payload, keys.numel())
+    if pw not in (0, 8):
+        raise ValueError("zsort_stable_p64 takes an 8-byte payload")
+    _check("zsort_stable_p64", lib().zsort_stable_p64(_keys_ptr(keys), p, keys.numel(),
+                                                      _stream(stream)))
+
+
+def zsort_stable_ex(keys, payload=None, cfg=None, stream=None):
+    p, pw = _pay(payload, keys.numel())
+    _check("zsort_stable_ex", lib().zsort_stable_ex(_keys_ptr(keys), p, pw, keys.numel(),
+                                                    _cfg(cfg), _stream(stream)))
+
+
+def zsort_stable_segmented(keys, seg_offsets, payload=None, cfg=None, stream=None):
+    import torch
+    if (not seg_offsets.is_cuda or seg_offsets.dtype != torch.int64
+            or not seg_offsets.is_contiguous()):
+        raise ValueError("seg_offsets must be a contiguous int64 CUDA tensor")
+    p, pw = _pay(payload, keys.numel())
+    _check("zsort_stable_segmented", lib().zsort_stable_segmented(
+        _keys_ptr(keys), p, pw, keys.numel(), ctypes.c_void_p(seg_offsets.data_ptr()),
+        seg_offsets.numel() - 1, _cfg(cfg), _stream(stream)))
+
+
+def zsort_workspace_bytes(n, payload_bytes=4, num_segments=0, cfg=None) -> int:
+    return int(lib().zsort_workspace_bytes(n, payload_bytes, num_segments, _cfg(cfg)))
+
+
+def zsort_get_last_stats(stream=None) -> dict:
+    s = ZsortStats()
+    _check("zsort_get_last_stats", lib().zsort_get_last_stats(_stream(stream), ctypes.byref(s)))
+    L = s.levels
+    return dict(levels=L, device_error=s.device_error, identical=s.identical,
+                range_mapped=s.range_mapped, leaf_groups=s.leaf_groups, n=s.n,
+                payload_bytes=s.payload_bytes,
+                keys_per_level=list(s.keys_per_level[:L]),
+                mkeys_per_level=list(s.mkeys_per_level[:L]),
+                segs_per_level=list(s.segs_per_level[:L]), model_bytes=s.model_bytes)
+
+
+def zsort_debug_level0(keys, payload=None, cfg=None, stream=None):
+    """One distribution pass of the root; returns (cluster keys, cluster payload)."""
+    import torch
+    p, pw = _pay(payload, keys.numel())
+    ok = torch.empty_like(keys)
+    op = torch.empty_like(payload) if payload is not None else None
+    _check("zsort_debug_level0", lib().zsort_debug_level0(
+        _keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg), ctypes.c_void_p(ok.data_ptr()),
+        ctypes.c_void_p(op.data_ptr()) if op is not None else None, _stream(stream)))
+    return ok, op
+
+
+def zsort_stable_traced(keys, payload=None, cfg=None, trace_cap=1 << 16, hist_cap=1 << 22,
+                        stream=None):
+    """Sort and return (records, histograms) of every subproblem above the cutoff."""
+    p, pw = _pay(payload, keys.numel())
+    rec = np.zeros(trace_cap, dtype=TRACE_REC)
+    hist = np.zeros(hist_cap, dtype=np.uint32)
+    counts = np.zeros(2, dtype=np.int64)
+    rc = lib().zsort_stable_traced(_keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg),
+                                   rec.ctypes.data, trace_cap, hist.ctypes.data, hist_cap,
+                                   counts.ctypes.data, _stream(stream))
+    _check("zsort_stable_traced", rc)
+    return rec[: min(int(counts[0]), trace_cap)], hist[: int(counts[1])]
+
+
+def zsort_release():
+    _check("zsort_release", lib().zsort_release())
+
+
+def sort(keys, payload=None, cfg=None, stream=None):
+    """In-place stable sort of keys (u64 bits in an int64/uint64 tensor) with an
+    optional 4- or 8-byte payload."""
+    zsort_stable_ex(keys, payload, cfg, stream)
+    return keys, payload

@@ -1,0 +1,470 @@
+// zsort_api.cpp -- C-ABI of the zSort library: argument checks, workspace
+// planning and caching (one workspace per stream), and the launch sequence of
+// the breadth-first recursion.  All sorting work happens in the HIP kernels
+// of zsort_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+
+#include "zsort.h"
+#include "zsort_internal.h"
+
+namespace zs {
+hipError_t launch_reset(const Ws& ws, hipStream_t st);
+hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st);
+hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, uint64_t n,
+                                hipStream_t st);
+hipError_t launch_levels(const Ws& ws, int levels, int grid, bool with_local, hipStream_t st);
+}  // namespace zs
+
+namespace {
+
+using zs::Ws;
+
+struct Shape {
+  uint64_t n = 0;
+  int pw = 0, k = 0, cutoff = 0, chunk = 0;
+  int64_t nseg = 0;
+  int64_t trace_cap = 0, trace_hist_cap = 0;
+  bool operator==(const Shape& o) const {
+    return n == o.n && pw == o.pw && k == o.k && cutoff == o.cutoff && chunk == o.chunk &&
+           nseg == o.nseg && trace_cap == o.trace_cap && trace_hist_cap == o.trace_hist_cap;
+  }
+};
+
+struct Layout {
+  size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_status,
+      off_bstart, off_trace, off_thist, total;
+  uint32_t seg_cap, work_cap, leaf_cap, status_cap;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Layout plan(const Shape& s) {
+  Layout L{};
+  const uint64_t n = s.n, ch = (uint64_t)s.chunk;
+  const uint64_t seg_cap = n / ((uint64_t)s.cutoff + 1) + 1;
+  const uint64_t nchunks = (n + ch - 1) / ch;
+  const uint64_t work_cap = nchunks + seg_cap;
+  const uint64_t status_cap = 2 * nchunks + 2;
+  const uint64_t leaf_cap = 6 * seg_cap + (uint64_t)s.nseg + 16;
+  L.seg_cap = (uint32_t)seg_cap;
+  L.work_cap = (uint32_t)work_cap;
+  L.leaf_cap = (uint32_t)leaf_cap;
+  L.status_cap = (uint32_t)status_cap;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = align_up(o, 256);
+    o = at + bytes;
+    return at;
+  };
+  L.off_ctl = take(sizeof(zs::Ctl));
+  L.off_keys = take(n * 8);
+  L.off_pay = take(n * (size_t)s.pw);
+  for (int i = 0; i < 2; ++i) {
+    L.off_segs[i] = take(seg_cap * sizeof(zs::Seg));
+    L.off_work[i] = take(work_cap * 8);
+    L.off_leaves[i] = take(leaf_cap * sizeof(zs::Leaf));
+  }
+  L.off_status = take(status_cap * (size_t)s.k * 8);
+  L.off_bstart = take(seg_cap * (size_t)s.k * 4);
+  L.off_trace = take((size_t)s.trace_cap * sizeof(zs::TraceRec));
+  L.off_thist = take((size_t)s.trace_hist_cap * 4);
+  L.total = align_up(o, 256);
+  return L;
+}
+
+struct Workspace {
+  int device = -1;
+  char* base = nullptr;
+  size_t bytes = 0;
+  Shape shape;
+  Layout lay{};
+  bool laid_out = false;
+  uint64_t calls = 0;
+  // last call
+  uint64_t last_n = 0;
+  int last_pw = 0;
+  bool has_last = false;
+};
+
+std::mutex g_mu;
+std::unordered_map<hipStream_t, Workspace*> g_ws;
+int g_last_hip = 0;
+int g_cu_count = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  if (e == hipErrorOutOfMemory) return ZSORT_ENOMEM;
+  return ZSORT_EHIP;
+}
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+int check_cfg(const zsort_config* c) {
+  if (c->k < 16 || c->k > zs::kKMax) return ZSORT_EINVAL;
+  if (c->cutoff < 1 || c->cutoff > zs::kLocalCap / 2) return ZSORT_EINVAL;
+  if (c->max_zlevels < 0 || c->max_zlevels > 16) return ZSORT_EINVAL;
+  if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
+  return ZSORT_OK;
+}
+
+int floor_log2(int k) {
+  int lb = 0;
+  while ((2 << lb) <= k) ++lb;
+  return lb;
+}
+
+int levels_for(const zsort_config& c) {
+  const int lb = floor_log2(c.k);
+  const int L = c.max_zlevels + (64 + lb - 1) / lb + 2;
+  return std::min(L, zs::kMaxLevels);
+}
+
+// Finds (or grows) the stream's workspace and lays it out for `s`.
+int acquire(hipStream_t st, const Shape& s, Workspace** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (!g_cu_count) {
+    e = hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  Workspace*& w = g_ws[st];
+  if (!w) w = new Workspace();
+  if (w->device != -1 && w->device != dev) return ZSORT_EINVAL;  // stream of another device
+  const Layout L = plan(s);
+  const bool same = w->laid_out && w->shape == s;
+  if (!same) {
+    if (capturing(st)) return ZSORT_ECAPTURE;
+    if (L.total > w->bytes) {
+      if (w->base) {
+        e = hipFree(w->base);
+        if (e != hipSuccess) return hip_fail(e);
+        w->base = nullptr;
+        w->bytes = 0;
+      }
+      void* p = nullptr;
+      e = hipMalloc(&p, L.total);
+      if (e != hipSuccess) return hip_fail(e);
+      w->base = (char*)p;
+      w->bytes = L.total;
+      e = hipMemsetAsync(w->base, 0, sizeof(zs::Ctl), st);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    // fresh look-back region: no stale word may carry a live tag
+    e = hipMemsetAsync(w->base + L.off_status, 0, (size_t)L.status_cap * (size_t)s.k * 8, st);
+    if (e != hipSuccess) return hip_fail(e);
+    w->device = dev;
+    w->shape = s;
+    w->lay = L;
+    w->laid_out = true;
+    w->calls = 0;
+  } else if (w->calls && (w->calls % 65536u) == 0) {
+    if (capturing(st)) return ZSORT_ECAPTURE;
+    e = hipMemsetAsync(w->base + L.off_status, 0, (size_t)L.status_cap * (size_t)s.k * 8, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  *out = w;
+  return ZSORT_OK;
+}
+
+Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int pw) {
+  const Layout& L = w->lay;
+  Ws ws;
+  std::memset(&ws, 0, sizeof ws);
+  ws.keys[0] = keys;
+  ws.keys[1] = (uint64_t*)(w->base + L.off_keys);
+  ws.pay[0] = pay;
+  ws.pay[1] = pw ? (void*)(w->base + L.off_pay) : nullptr;
+  for (int i = 0; i < 2; ++i) {
+    ws.segs[i] = (zs::Seg*)(w->base + L.off_segs[i]);
+    ws.work[i] = (uint64_t*)(w->base + L.off_work[i]);
+    ws.leaves[i] = (zs::Leaf*)(w->base + L.off_leaves[i]);
+  }
+  ws.status = (uint64_t*)(w->base + L.off_status);
+  ws.bstart = (uint32_t*)(w->base + L.off_bstart);
+  ws.ctl = (zs::Ctl*)(w->base + L.off_ctl);
+  ws.trace = w->shape.trace_cap ? (zs::TraceRec*)(w->base + L.off_trace) : nullptr;
+  ws.trace_hist = w->shape.trace_hist_cap ? (uint32_t*)(w->base + L.off_thist) : nullptr;
+  ws.trace_cap = (uint32_t)w->shape.trace_cap;
+  ws.trace_hist_cap = (uint32_t)w->shape.trace_hist_cap;
+  ws.seg_cap = L.seg_cap;
+  ws.work_cap = L.work_cap;
+  ws.leaf_cap = L.leaf_cap;
+  ws.status_cap = L.status_cap;
+  ws.p.k = c.k;
+  ws.p.lb = floor_log2(c.k);
+  ws.p.cutoff = c.cutoff;
+  ws.p.max_zlevels = c.max_zlevels;
+  ws.p.chunk = c.chunk;
+  ws.p.pw = pw;
+  return ws;
+}
+
+int grid_size() { return std::max(1, g_cu_count) * 2; }
+
+struct Call {
+  uint64_t* keys;
+  void* pay;
+  int pw;
+  uint64_t n;
+  const int64_t* off;  // segmented form
+  int32_t nseg;
+  zsort_config cfg;
+  int64_t trace_cap, hist_cap;
+  bool level0_only;
+};
+
+int run(const Call& c, hipStream_t st, Workspace** wout) {
+  Shape s;
+  s.n = c.n;
+  s.pw = c.pw;
+  s.k = c.cfg.k;
+  s.cutoff = c.cfg.cutoff;
+  s.chunk = c.cfg.chunk;
+  s.nseg = c.off ? c.nseg : 0;
+  s.trace_cap = c.trace_cap;
+  s.trace_hist_cap = c.hist_cap;
+  Workspace* w = nullptr;
+  int rc = acquire(st, s, &w);
+  if (rc) return rc;
+  const Ws ws = make_ws(w, c.keys, c.pay, c.cfg, c.pw);
+  hipError_t e = zs::launch_reset(ws, st);
+  if (e == hipSuccess) {
+    if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
+    else e = zs::launch_init_single(ws, c.n, st);
+  }
+  if (e == hipSuccess) {
+    if (c.level0_only) e = zs::launch_levels(ws, 1, grid_size(), false, st);
+    else e = zs::launch_levels(ws, levels_for(c.cfg), grid_size(), true, st);
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  w->calls++;
+  w->last_n = c.n;
+  w->last_pw = c.pw;
+  w->has_last = true;
+  if (wout) *wout = w;
+  return ZSORT_OK;
+}
+
+int resolve_cfg(const zsort_config* in, zsort_config* out) {
+  zsort_default_config(out);
+  if (in) *out = *in;
+  return check_cfg(out);
+}
+
+int common_checks(const uint64_t* keys, const void* pay, int pw, size_t n) {
+  if (pw != 0 && pw != 4 && pw != 8) return ZSORT_EINVAL;
+  if (n > 0x7FFFFFFFull) return ZSORT_EINVAL;
+  if (n > 1 && !keys) return ZSORT_EINVAL;
+  if (n > 1 && pw && !pay) return ZSORT_EINVAL;
+  return ZSORT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int zsort_default_config(zsort_config* cfg) {
+  if (!cfg) return ZSORT_EINVAL;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->k = 1024;
+  cfg->cutoff = 2048;
+  cfg->max_zlevels = 8;
+  cfg->chunk = 16384;
+  return ZSORT_OK;
+}
+
+int zsort_stable_ex(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                    const zsort_config* cfg, void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c);
+  if (rc) return rc;
+  if (n <= 1) return ZSORT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Call call{keys, payload_bytes ? payload : nullptr, payload_bytes, (uint64_t)n, nullptr, 0, c,
+            0, 0, false};
+  return run(call, (hipStream_t)stream, nullptr);
+}
+
+int zsort_stable(uint64_t* keys, uint32_t* payload, size_t n, void* stream) {
+  return zsort_stable_ex(keys, payload, payload ? 4 : 0, n, nullptr, stream);
+}
+
+int zsort_stable_p64(uint64_t* keys, uint64_t* payload, size_t n, void* stream) {
+  return zsort_stable_ex(keys, payload, payload ? 8 : 0, n, nullptr, stream);
+}
+
+int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                           const int64_t* seg_offsets, int32_t num_segments,
+                           const zsort_config* cfg, void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  if (num_segments < 0 || (num_segments > 0 && !seg_offsets)) return ZSORT_EINVAL;
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c);
+  if (rc) return rc;
+  if (n <= 1 || num_segments == 0) return ZSORT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Call call{keys, payload_bytes ? payload : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
+            num_segments, c, 0, 0, false};
+  return run(call, (hipStream_t)stream, nullptr);
+}
+
+size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
+                             const zsort_config* cfg) {
+  zsort_config c;
+  if (resolve_cfg(cfg, &c)) return 0;
+  if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return 0;
+  if (num_segments < 0 || n > 0x7FFFFFFFull) return 0;
+  Shape s;
+  s.n = n;
+  s.pw = payload_bytes;
+  s.k = c.k;
+  s.cutoff = c.cutoff;
+  s.chunk = c.chunk;
+  s.nseg = num_segments;
+  return plan(s).total;
+}
+
+int zsort_get_last_stats(void* stream, zsort_stats* out) {
+  if (!out) return ZSORT_EINVAL;
+  std::memset(out, 0, sizeof *out);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find((hipStream_t)stream);
+  if (it == g_ws.end() || !it->second->has_last) return ZSORT_EINVAL;
+  Workspace* w = it->second;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  zs::Ctl ctl;
+  e = hipMemcpy(&ctl, w->base + w->lay.off_ctl, sizeof ctl, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  out->device_error = (int32_t)ctl.error;
+  out->identical = ctl.n_ident;
+  out->range_mapped = ctl.n_rmap;
+  out->leaf_groups = ctl.n_leafgroups;
+  out->payload_bytes = w->last_pw;
+  out->n = w->last_n;
+  int levels = 0;
+  double bytes = 0;
+  const double kp = 8.0 + w->last_pw;
+  for (int L = 0; L < zs::kMaxLevels && L < ZSORT_MAX_LEVELS; ++L) {
+    out->keys_per_level[L] = ctl.lvl_keys[L];
+    out->mkeys_per_level[L] = ctl.lvl_mkeys[L];
+    out->segs_per_level[L] = ctl.lvl_segs[L];
+    if (ctl.lvl_mkeys[L]) levels = L + 1;
+    bytes += 8.0 * (double)ctl.lvl_mkeys[L] + (8.0 + 2 * kp) * (double)ctl.lvl_keys[L];
+  }
+  bytes += 2 * kp * (double)w->last_n;
+  out->levels = levels;
+  out->model_bytes = bytes;
+  return ZSORT_OK;
+}
+
+int zsort_debug_level0(const uint64_t* keys, const void* payload, int payload_bytes, size_t n,
+                       const zsort_config* cfg, uint64_t* out_keys, void* out_payload,
+                       void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c);
+  if (rc) return rc;
+  if (n <= (size_t)c.cutoff || !out_keys || (payload_bytes && !out_payload)) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Call call{const_cast<uint64_t*>(keys), payload_bytes ? const_cast<void*>(payload) : nullptr,
+            payload_bytes, (uint64_t)n, nullptr, 0, c, 0, 0, true};
+  Workspace* w = nullptr;
+  rc = run(call, st, &w);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(out_keys, w->base + w->lay.off_keys, n * 8,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && payload_bytes)
+    e = hipMemcpyAsync(out_payload, w->base + w->lay.off_pay, n * (size_t)payload_bytes,
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  return ZSORT_OK;
+}
+
+int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                        const zsort_config* cfg, zsort_trace_rec* trace, int64_t trace_cap,
+                        uint32_t* hist, int64_t hist_cap, int64_t counts[2], void* stream) {
+  static_assert(sizeof(zsort_trace_rec) == sizeof(zs::TraceRec), "trace record layout");
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c);
+  if (rc) return rc;
+  if (trace_cap < 0 || hist_cap < 0 || (trace_cap && !trace) || (hist_cap && !hist) || !counts)
+    return ZSORT_EINVAL;
+  if (trace_cap > 0xFFFFFFF || hist_cap > 0xFFFFFFFF) return ZSORT_EINVAL;
+  counts[0] = counts[1] = 0;
+  if (n <= 1) return ZSORT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Call call{keys, payload_bytes ? payload : nullptr, payload_bytes, (uint64_t)n, nullptr, 0, c,
+            std::max<int64_t>(trace_cap, 1), std::max<int64_t>(hist_cap, 1), false};
+  Workspace* w = nullptr;
+  rc = run(call, st, &w);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  zs::Ctl ctl;
+  e = hipMemcpy(&ctl, w->base + w->lay.off_ctl, sizeof ctl, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  counts[0] = ctl.ntrace;
+  counts[1] = std::min<int64_t>(ctl.ntrace_hist, hist_cap);
+  const int64_t nrec = std::min<int64_t>(ctl.ntrace, trace_cap);
+  if (nrec) {
+    e = hipMemcpy(trace, w->base + w->lay.off_trace, (size_t)nrec * sizeof(zsort_trace_rec),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (counts[1]) {
+    e = hipMemcpy(hist, w->base + w->lay.off_thist, (size_t)counts[1] * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ctl.error ? ZSORT_EDEVICE : ZSORT_OK;
+}
+
+int zsort_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = ZSORT_OK;
+  for (auto& kv : g_ws) {
+    if (kv.second->base) {
+      hipError_t e = hipFree(kv.second->base);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    delete kv.second;
+  }
+  g_ws.clear();
+  return rc;
+}
+
+int zsort_last_hip_error(void) { return g_last_hip; }
+
+const char* zsort_strerror(int status) {
+  switch (status) {
+    case ZSORT_OK: return "ok";
+    case ZSORT_EINVAL: return "invalid argument";
+    case ZSORT_ENOMEM: return "device allocation failed";
+    case ZSORT_EHIP: return "HIP runtime error";
+    case ZSORT_ECAPTURE: return "would allocate during stream capture";
+    case ZSORT_EUNSUPPORTED: return "configuration not supported";
+    case ZSORT_EDEVICE: return "device-side limit hit";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

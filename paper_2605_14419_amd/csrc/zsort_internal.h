@@ -1,0 +1,134 @@
+// zsort_internal.h -- device data structures shared by the HIP kernels and the
+// host planner of the zSort library (not part of the public C-ABI).
+//
+// The sort is a breadth-first version of zSort's recursion (Section III and
+// Algorithm 1 of "zSort: Stable Distribution Sort using Z-Score
+// Partitioning"): level L holds every subproblem ("segment") of depth L, and
+// each level runs four kernels over all of its segments at once:
+//   moments  -- exact integer min/max/sum/sum of squares, then finalize
+//               (mean, std, Zmin, scale -> the map's A and B)
+//   hist     -- per-chunk cluster histogram, decoupled look-back prefix
+//               across the chunks of a segment, and (last chunk) the
+//               exclusive scan + classification of the clusters
+//   scatter  -- stable scatter of key+payload to the other buffer
+//   local    -- in-LDS stable sort of the small clusters of this level
+// The recursion never returns to the host: each kernel reads its work count
+// from device memory.
+#pragma once
+#include <stdint.h>
+
+namespace zs {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // threads per workgroup, 4 waves
+constexpr int kWaves = kBlock / kWave;
+constexpr int kMaxLevels = 40;
+constexpr int kKMax = 4096;            // largest clusters-per-pass supported
+constexpr int kLocalCap = 4096;        // largest leaf group the local sort takes
+
+// segment kinds, as in the recursion records
+enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3 };
+// segment flags
+enum : uint32_t { F_RMAP = 1u, F_ROOT = 2u };
+// leaf-group flags
+enum : uint32_t { LF_COPY = 1u };
+
+struct __attribute__((aligned(16))) Seg {
+  uint64_t start;        // first position in the array
+  uint64_t count;        // number of keys
+  uint64_t o_parent;     // parent's minimum (frame of e)
+  double e;              // estimated mean in the parent's frame (z-map child)
+  int32_t depth;
+  uint32_t flags;
+  uint32_t first_work;   // first chunk's index in the level's work list
+  uint32_t nchunks;
+  uint32_t status_base;  // first look-back slot (segments of > 1 chunk)
+  uint32_t done;         // chunks that finished the moments pass
+  int32_t parent;        // index of the parent in the previous level's list
+  int32_t pad0;
+  // exact moment accumulators (32-bit digit sums of x and x^2)
+  uint64_t acc[8];
+  uint64_t amin, amax;
+  // results of finalize
+  uint64_t o, M;
+  uint64_t s1[2];        // sum (x - o)
+  uint64_t s2[4];        // sum (x - o)^2
+  double m, sigma, zmin, A, B;
+  int32_t kind;
+  int32_t shift;         // range-map shift
+};
+
+struct __attribute__((aligned(16))) Leaf {
+  uint64_t start;
+  uint32_t count;
+  uint32_t flags;        // LF_COPY: identical keys, copy only
+  uint32_t src;          // 0: keys are in the caller's buffer, 1: in the alternate buffer
+  uint32_t pad[3];
+};
+
+// Control block in device memory.  Lists alternate between two slots: the
+// segments (and their work items and leaves) of level L live in slot L & 1.
+struct __attribute__((aligned(64))) Ctl {
+  uint32_t nseg[2];
+  uint32_t nwork[2];
+  uint32_t nleaf[2];
+  uint32_t nstatus[2];
+  uint32_t tick[kMaxLevels];     // in-order chunk tickets of the hist pass
+  uint32_t epoch;                // changes every call; tags look-back words
+  uint32_t error;                // nonzero: a capacity or wait limit was hit
+  uint32_t ntrace;
+  uint32_t ntrace_hist;
+  // statistics of the call
+  uint64_t lvl_keys[kMaxLevels]; // keys distributed at each level
+  uint64_t lvl_mkeys[kMaxLevels];// keys whose moments were taken at each level
+  uint32_t lvl_segs[kMaxLevels];
+  uint32_t n_ident;
+  uint32_t n_rmap;
+  uint32_t n_leafgroups;
+  uint32_t max_level;
+};
+
+enum : uint32_t { ERR_SEGCAP = 1u, ERR_WORKCAP = 2u, ERR_LEAFCAP = 4u, ERR_STATUSCAP = 8u,
+                  ERR_SPIN = 16u, ERR_SCATTER = 32u, ERR_OFFSETS = 0x100u };
+
+// Debug trace record (written only when the trace buffer is given).
+struct TraceRec {
+  int32_t depth;
+  int32_t kind;
+  uint64_t start, count;
+  uint64_t o, M;
+  uint64_t s1[2];
+  uint64_t s2[4];
+  double m, sigma, zmin, A, B;
+  int32_t shift;
+  int32_t nonempty;
+  int64_t hist_off;
+};
+
+struct Params {
+  int32_t k;             // clusters per pass
+  int32_t lb;            // floor(log2 k), range-map bits per pass
+  int32_t cutoff;        // leaf size
+  int32_t max_zlevels;
+  int32_t chunk;         // keys per work item
+  int32_t pw;            // payload bytes: 0, 4, 8
+};
+
+// Everything a kernel needs, by value.
+struct Ws {
+  uint64_t* keys[2];     // [0] caller's buffer, [1] alternate buffer
+  void* pay[2];
+  Seg* segs[2];
+  uint64_t* work[2];     // (segment << 32) | chunk
+  Leaf* leaves[2];
+  uint64_t* status;      // look-back words, [slot][k]
+  uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
+  Ctl* ctl;
+  TraceRec* trace;       // may be null
+  uint32_t* trace_hist;
+  uint32_t trace_cap, trace_hist_cap;
+  uint32_t seg_cap, work_cap, leaf_cap, status_cap;
+  Params p;
+};
+
+}  // namespace zs

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Integer work is compared bit for bit: the sorted keys and payloads, the exact
+moments, the histograms and the cluster array after a pass.  The binary64
+statistics are compared bit for bit too, because both sides evaluate the same
+correctly rounded operations in the same order.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.invariants import check_stable_sorted
+
+torch = pytest.importorskip("torch")
+zs = pytest.importorskip("paper_2605_14419_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+ALPHABET = [0, 1, 2, 2**63 - 1, 2**63, 2**64 - 2, 2**64 - 1]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def to_dev(keys, pay=None):
+    tk = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).to(DEV)
+    tp = None
+    if pay is not None:
+        v = pay.view(np.int32) if pay.dtype.itemsize == 4 else pay.view(np.int64)
+        tp = torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+    return tk, tp
+
+
+def from_dev(tk, tp, pdtype=np.uint32):
+    k = tk.cpu().numpy().view(np.uint64)
+    p = None if tp is None else tp.cpu().numpy().view(pdtype)
+    return k, p
+
+
+def gpu_sort(keys, pay, cfg):
+    tk, tp = to_dev(keys, pay)
+    zs.zsort_stable_ex(tk, tp, cfg)
+    torch.cuda.synchronize()
+    st = zs.zsort_get_last_stats() if keys.size > 1 else {"device_error": 0}
+    k, p = from_dev(tk, tp, None if pay is None else pay.dtype)
+    return k, p, st
+
+
+CFG = dict(k=1024, cutoff=2048, max_zlevels=8, chunk=16384)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 64, 65, 2047, 2048, 2049, 4097, 16385, 40000])
+def test_small_sizes_and_ragged_tails(n):
+    say(f"case small n={n}")
+    x, idx = synth.make("dup_heavy", max(n, 1))
+    x, idx = x[:n], idx[:n]
+    for cfg in [CFG, dict(CFG, cutoff=16, k=16, chunk=2048)]:
+        k, p, st = gpu_sort(x, idx, cfg)
+        assert st["device_error"] == 0, st
+        ok, oi, _ = oracle.sort(x, idx, k=cfg["k"], cutoff=cfg["cutoff"], max_zlevels=8)
+        assert np.array_equal(k, ok) and np.array_equal(p, oi), cfg
+
+
+def test_exhaustive_tiny_segmented():
+    """every array of length 4 over extreme values, one segmented call,
+    cutoff 1 so every array of >= 2 keys is distributed"""
+    arrays = np.array(list(itertools.product(ALPHABET, repeat=4)), dtype=np.uint64)
+    x = arrays.reshape(-1)
+    off = np.arange(0, x.size + 1, 4, dtype=np.int64)
+    idx = np.tile(np.arange(4, dtype=np.uint32), arrays.shape[0])
+    for cfg in [dict(k=16, cutoff=1, max_zlevels=8, chunk=2048),
+                dict(k=16, cutoff=1, max_zlevels=0, chunk=2048),
+                dict(k=4096, cutoff=1, max_zlevels=1, chunk=2048)]:
+        say(f"case exhaustive4 {cfg}")
+        tk, tp = to_dev(x, idx)
+        toff = torch.from_numpy(off).to(DEV)
+        zs.zsort_stable_segmented(tk, toff, tp, cfg)
+        torch.cuda.synchronize()
+        assert zs.zsort_get_last_stats()["device_error"] == 0
+        k, p = from_dev(tk, tp)
+        ok, oi = oracle.sort_segmented(x, off, idx, k=cfg["k"], cutoff=1,
+                                       max_zlevels=cfg["max_zlevels"])
+        assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
+WORKLOADS = ["uniform", "normal", "dup_heavy", "partial", "descending", "lognormal", "zipf",
+             "gmm"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_workloads_vs_oracle(name):
+    n = 3 * 10**5 + 17
+    x, idx = synth.make(name, n)
+    say(f"case workload {name} n={n}")
+    k, p, st = gpu_sort(x, idx, CFG)
+    assert st["device_error"] == 0, st
+    ok, oi, _ = oracle.sort(x, idx, **{kk: CFG[kk] for kk in ("k", "cutoff", "max_zlevels")})
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
+@pytest.mark.parametrize("cfg", [dict(k=16, cutoff=64, max_zlevels=8, chunk=2048),
+                                 dict(k=256, cutoff=256, max_zlevels=2, chunk=4096),
+                                 dict(k=4096, cutoff=2048, max_zlevels=8, chunk=32768),
+                                 dict(k=1000, cutoff=100, max_zlevels=0, chunk=16384),
+                                 dict(k=3162, cutoff=96, max_zlevels=16, chunk=2048)])
+def test_configs_trace_parity(cfg):
+    """level by level: every subproblem's moments, statistics bits, kind and
+    histogram agree with the oracle under the same k / cutoff / depth guard"""
+    for name in ["uniform", "normal", "zipf", "gmm", "dup_heavy"]:
+        n = 200_003
+        x, idx = synth.make(name, n)
+        say(f"case trace {name} {cfg}")
+        tk, tp = to_dev(x, idx)
+        rec, hist = zs.zsort_stable_traced(tk, tp, cfg)
+        k, p = from_dev(tk, tp)
+        ok, oi, info, otr, ohist = oracle.sort(
+            x, idx, k=cfg["k"], cutoff=cfg["cutoff"], max_zlevels=cfg["max_zlevels"], trace=True)
+        assert np.array_equal(k, ok) and np.array_equal(p, oi)
+        assert len(rec) == len(otr) == info[0]
+        g = {(int(r["depth"]), int(r["start"])): r for r in rec}
+        assert len(g) == len(rec)
+        kk = cfg["k"]
+        for r in otr:
+            q = g[(int(r["depth"]), int(r["start"]))]
+            for f in ["kind", "count", "o", "M", "shift"]:
+                assert q[f] == r[f], (f, r, q)
+            assert np.array_equal(q["s1"], r["s1"]) and np.array_equal(q["s2"], r["s2"])
+            for f in ["m", "sigma", "zmin", "A", "B"]:
+                assert np.float64(q[f]).tobytes() == np.float64(r[f]).tobytes(), (f, r, q)
+            if r["kind"] in (oracle.KIND_ZMAP, oracle.KIND_RMAP):
+                assert q["nonempty"] == r["nonempty"]
+                gh = hist[q["hist_off"]: q["hist_off"] + kk]
+                oh = ohist[r["hist_off"]: r["hist_off"] + kk]
+                assert np.array_equal(gh, oh)
+
+
+@pytest.mark.parametrize("name", ["uniform_2p20", "normal", "dup_heavy"])
+def test_level0_cluster_array(name):
+    n = 1 << 20
+    x, idx = synth.make(name, n)
+    say(f"case level0 {name}")
+    for cfg in [CFG, dict(CFG, k=4096, chunk=32768), dict(CFG, max_zlevels=0)]:
+        tk, tp = to_dev(x, idx)
+        ck, cp = zs.zsort_debug_level0(tk, tp, cfg)
+        gk, gp = from_dev(ck, cp)
+        assert np.array_equal(from_dev(tk, tp)[0], x)   # input untouched
+        ok, oi, rec, hist = oracle.level0(x, idx, k=cfg["k"], cutoff=cfg["cutoff"],
+                                          max_zlevels=cfg["max_zlevels"])
+        assert np.array_equal(gk, ok) and np.array_equal(gp, oi)
+
+
+@pytest.mark.parametrize("pw", [0, 4, 8])
+def test_payload_widths(pw):
+    n = 123_457
+    x, pay = synth.make("zipf", n, payload_bytes=pw)
+    say(f"case payload {pw}")
+    k, p, st = gpu_sort(x, pay, CFG)
+    ok, op, _ = oracle.sort(x, pay, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(k, ok)
+    if pw:
+        assert np.array_equal(p, op)
+
+
+def test_segmented_vs_oracle():
+    keys, off, idx = synth.segments(512, 77, median=3000, hi=200_000)
+    say(f"case segmented n={keys.size}")
+    tk, tp = to_dev(keys, idx)
+    toff = torch.from_numpy(off).to(DEV)
+    zs.zsort_stable_segmented(tk, toff, tp, CFG)
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] == 0
+    k, p = from_dev(tk, tp)
+    ok, oi = oracle.sort_segmented(keys, off, idx, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
+def test_segmented_malformed_offsets_move_nothing():
+    keys, idx = synth.make("uniform", 10_000)
+    off = np.array([0, 5000, 4000, 10_000], dtype=np.int64)  # decreasing
+    say("case segmented malformed")
+    tk, tp = to_dev(keys, idx)
+    zs.zsort_stable_segmented(tk, torch.from_numpy(off).to(DEV), tp, CFG)
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] & 0x100
+    k, p = from_dev(tk, tp)
+    assert np.array_equal(k, keys) and np.array_equal(p, idx)
+
+
+def test_repeat_calls_identical():
+    x, idx = synth.make("lognormal", 500_000)
+    say("case repeat")
+    outs = [gpu_sort(x, idx, CFG)[:2] for _ in range(3)]
+    for k, p in outs[1:]:
+        assert np.array_equal(k, outs[0][0]) and np.array_equal(p, outs[0][1])
+
+
+@pytest.mark.parametrize("name", ["uniform", "normal", "dup_heavy", "partial", "descending"])
+def test_ten_million_vs_oracle(name):
+    """the five 10^7 arrays of the plain-path workload, full size"""
+    n = 10**7
+    x, idx = synth.make(name, n)
+    say(f"case 1e7 {name}")
+    k, p, st = gpu_sort(x, idx, CFG)
+    assert st["device_error"] == 0, st
+    ok, oi, _ = oracle.sort(x, idx, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
