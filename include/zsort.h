@@ -118,10 +118,12 @@ size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
  *   keys_per_level    keys distributed at each level
  *   segs_per_level    subproblems distributed at each level
  *   mkeys_per_level   keys whose moments were taken at each level
+ *   local_keys        keys the local kernel sorted or copied into place
  *   model_bytes       algorithmic HBM bytes of the executed pass structure:
- *                     per level 8 B/key (moments) + 8 B/key (histogram) +
- *                     2(8+P) B/key (scatter), plus 2(8+P) B/key for the
- *                     final local sort / copy
+ *                     8 B per key of a moments pass, 8 B per key of a
+ *                     histogram pass, 2(8+P) B per key of a scatter pass and
+ *                     2(8+P) B per local-sorted or copied key (P = payload
+ *                     bytes)
  */
 #define ZSORT_MAX_LEVELS 40
 typedef struct zsort_stats {
@@ -135,6 +137,7 @@ typedef struct zsort_stats {
   uint64_t keys_per_level[ZSORT_MAX_LEVELS];
   uint64_t mkeys_per_level[ZSORT_MAX_LEVELS];
   uint32_t segs_per_level[ZSORT_MAX_LEVELS];
+  uint64_t local_keys;
   double model_bytes;
 } zsort_stats;
 
@@ -182,6 +185,24 @@ typedef struct zsort_trace_rec {
 int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t n,
                         const zsort_config* cfg, zsort_trace_rec* trace, int64_t trace_cap,
                         uint32_t* hist, int64_t hist_cap, int64_t counts[2], void* stream);
+
+/*
+ * Per-kernel device time.  Between zsort_profile_begin(stream) and
+ * zsort_profile_end(stream, out) every kernel the library launches on
+ * `stream` is bracketed by a pair of hipEvents recorded on that same stream;
+ * _end synchronises the stream and sums the elapsed times per kernel kind:
+ * index 0 moments, 1 finalize (statistics of the map), 2 histogram (with
+ * look-back and classification), 3 stable scatter, 4 local sort.
+ * launches[i] counts the launches, including those of levels that found no
+ * work.
+ */
+typedef struct zsort_kernel_times {
+  double ms[5];
+  uint64_t launches[5];
+} zsort_kernel_times;
+
+int zsort_profile_begin(void* stream);
+int zsort_profile_end(void* stream, zsort_kernel_times* out /* host */);
 
 /* Frees every cached workspace (synchronises the device). */
 int zsort_release(void);

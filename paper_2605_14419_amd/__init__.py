@@ -23,8 +23,9 @@ EXPORTED = [
     "zsort_default_config", "zsort_stable", "zsort_stable_p64", "zsort_stable_ex",
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
-    "zsort_strerror",
+    "zsort_strerror", "zsort_profile_begin", "zsort_profile_end",
 ]
+STAGES = ("moments", "finalize", "hist", "scatter", "local")
 
 
 class ZsortConfig(ctypes.Structure):
@@ -41,7 +42,12 @@ class ZsortStats(ctypes.Structure):
                 ("keys_per_level", ctypes.c_uint64 * MAX_LEVELS),
                 ("mkeys_per_level", ctypes.c_uint64 * MAX_LEVELS),
                 ("segs_per_level", ctypes.c_uint32 * MAX_LEVELS),
+                ("local_keys", ctypes.c_uint64),
                 ("model_bytes", ctypes.c_double)]
+
+
+class ZsortKernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_uint64 * 5)]
 
 
 TRACE_REC = np.dtype([
@@ -81,6 +87,8 @@ def lib():
         L.zsort_debug_level0.argtypes = [P, P, I, Z, P, P, P, P]
         L.zsort_stable_traced.argtypes = [P, P, I, Z, P, P, ctypes.c_int64, P, ctypes.c_int64,
                                           P, P]
+        L.zsort_profile_begin.argtypes = [P]
+        L.zsort_profile_end.argtypes = [P, P]
         L.zsort_strerror.argtypes = [I]
         L.zsort_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -190,7 +198,8 @@ def zsort_get_last_stats(stream=None) -> dict:
                 payload_bytes=s.payload_bytes,
                 keys_per_level=list(s.keys_per_level[:L]),
                 mkeys_per_level=list(s.mkeys_per_level[:L]),
-                segs_per_level=list(s.segs_per_level[:L]), model_bytes=s.model_bytes)
+                segs_per_level=list(s.segs_per_level[:L]), local_keys=s.local_keys,
+                model_bytes=s.model_bytes)
 
 
 def zsort_debug_level0(keys, payload=None, cfg=None, stream=None):
@@ -217,6 +226,17 @@ def zsort_stable_traced(keys, payload=None, cfg=None, trace_cap=1 << 16, hist_ca
                                    counts.ctypes.data, _stream(stream))
     _check("zsort_stable_traced", rc)
     return rec[: min(int(counts[0]), trace_cap)], hist[: int(counts[1])]
+
+
+def zsort_profile_begin(stream=None):
+    _check("zsort_profile_begin", lib().zsort_profile_begin(_stream(stream)))
+
+
+def zsort_profile_end(stream=None) -> dict:
+    """{stage: (total ms, launches)} for moments / finalize / hist / scatter / local."""
+    t = ZsortKernelTimes()
+    _check("zsort_profile_end", lib().zsort_profile_end(_stream(stream), ctypes.byref(t)))
+    return {name: (t.ms[i], int(t.launches[i])) for i, name in enumerate(STAGES)}
 
 
 def zsort_release():

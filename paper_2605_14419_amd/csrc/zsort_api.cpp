@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "zsort.h"
 #include "zsort_internal.h"
@@ -17,7 +18,8 @@ hipError_t launch_reset(const Ws& ws, hipStream_t st);
 hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st);
 hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, uint64_t n,
                                 hipStream_t st);
-hipError_t launch_levels(const Ws& ws, int levels, int grid, bool with_local, hipStream_t st);
+hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st);
+int stage_blocks_per_cu(int k, int pw, int stage);
 }  // namespace zs
 
 namespace {
@@ -36,7 +38,8 @@ struct Shape {
 };
 
 struct Layout {
-  size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_status,
+  size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
+      off_status,
       off_bstart, off_trace, off_thist, total;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap;
 };
@@ -50,7 +53,10 @@ Layout plan(const Shape& s) {
   const uint64_t nchunks = (n + ch - 1) / ch;
   const uint64_t work_cap = nchunks + seg_cap;
   const uint64_t status_cap = 2 * nchunks + 2;
-  const uint64_t leaf_cap = 6 * seg_cap + (uint64_t)s.nseg + 16;
+  // leaf jobs of one level: runs (<= children + segments), windows of kWindow
+  // keys, leaves above kWindow (each may also end a group), copy pieces
+  const uint64_t leaf_cap = 4 * seg_cap + 4 * (n / zs::kWindow) + n / zs::kCopyChunk +
+                            (uint64_t)s.nseg + 64;
   L.seg_cap = (uint32_t)seg_cap;
   L.work_cap = (uint32_t)work_cap;
   L.leaf_cap = (uint32_t)leaf_cap;
@@ -68,6 +74,7 @@ Layout plan(const Shape& s) {
     L.off_segs[i] = take(seg_cap * sizeof(zs::Seg));
     L.off_work[i] = take(work_cap * 8);
     L.off_leaves[i] = take(leaf_cap * sizeof(zs::Leaf));
+    L.off_leavesw[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
   L.off_status = take(status_cap * (size_t)s.k * 8);
   L.off_bstart = take(seg_cap * (size_t)s.k * 4);
@@ -89,7 +96,36 @@ struct Workspace {
   uint64_t last_n = 0;
   int last_pw = 0;
   bool has_last = false;
+  // per-kernel event timing (zsort_profile_begin / _end)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_stage;  // stage of each (start, end) pair
 };
+
+hipError_t next_event(Workspace* w, hipEvent_t* ev) {
+  if (w->ev_used == w->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    w->ev_pool.push_back(e);
+  }
+  *ev = w->ev_pool[w->ev_used++];
+  return hipSuccess;
+}
+
+// launches one stage, bracketed by events when the stream is being profiled
+hipError_t stage(Workspace* w, const Ws& ws, int L, int st_id, int grid, hipStream_t st) {
+  if (!w->prof) return zs::launch_stage(ws, L, st_id, grid, st);
+  hipEvent_t a, b;
+  hipError_t e = next_event(w, &a);
+  if (e == hipSuccess) e = next_event(w, &b);
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = zs::launch_stage(ws, L, st_id, grid, st);
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) w->ev_stage.push_back(st_id);
+  return e;
+}
 
 std::mutex g_mu;
 std::unordered_map<hipStream_t, Workspace*> g_ws;
@@ -188,6 +224,7 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
     ws.segs[i] = (zs::Seg*)(w->base + L.off_segs[i]);
     ws.work[i] = (uint64_t*)(w->base + L.off_work[i]);
     ws.leaves[i] = (zs::Leaf*)(w->base + L.off_leaves[i]);
+    ws.leavesw[i] = (zs::Leaf*)(w->base + L.off_leavesw[i]);
   }
   ws.status = (uint64_t*)(w->base + L.off_status);
   ws.bstart = (uint32_t*)(w->base + L.off_bstart);
@@ -209,7 +246,23 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
   return ws;
 }
 
-int grid_size() { return std::max(1, g_cu_count) * 2; }
+// grid of a stage: every compute unit filled to the kernel's occupancy
+int grid_size(int k, int pw, int stage) {
+  static std::mutex mu;
+  static std::unordered_map<int, int> cache;
+  const int key = (k > 1024 ? 1 : 0) | (pw << 1) | (stage << 8);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  int per = 0;
+  if (it != cache.end()) {
+    per = it->second;
+  } else {
+    per = std::min(8, zs::stage_blocks_per_cu(k, pw, stage));
+    cache[key] = per;
+  }
+  if (stage == zs::STAGE_FINALIZE) return std::max(1, g_cu_count);
+  return std::max(1, g_cu_count) * per;
+}
 
 struct Call {
   uint64_t* keys;
@@ -242,9 +295,12 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
     if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
     else e = zs::launch_init_single(ws, c.n, st);
   }
-  if (e == hipSuccess) {
-    if (c.level0_only) e = zs::launch_levels(ws, 1, grid_size(), false, st);
-    else e = zs::launch_levels(ws, levels_for(c.cfg), grid_size(), true, st);
+  const int levels = c.level0_only ? 1 : levels_for(c.cfg);
+  for (int L = 0; L < levels && e == hipSuccess; ++L) {
+    for (int sid = 0; sid < zs::NSTAGES && e == hipSuccess; ++sid) {
+      if (c.level0_only && sid == zs::STAGE_LOCAL) continue;
+      e = stage(w, ws, L, sid, grid_size(c.cfg.k, c.pw, sid), st);
+    }
   }
   if (e != hipSuccess) return hip_fail(e);
   w->calls++;
@@ -365,7 +421,8 @@ int zsort_get_last_stats(void* stream, zsort_stats* out) {
     if (ctl.lvl_mkeys[L]) levels = L + 1;
     bytes += 8.0 * (double)ctl.lvl_mkeys[L] + (8.0 + 2 * kp) * (double)ctl.lvl_keys[L];
   }
-  bytes += 2 * kp * (double)w->last_n;
+  bytes += 2 * kp * (double)ctl.local_keys;
+  out->local_keys = ctl.local_keys;
   out->levels = levels;
   out->model_bytes = bytes;
   return ZSORT_OK;
@@ -438,6 +495,38 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
   return ctl.error ? ZSORT_EDEVICE : ZSORT_OK;
 }
 
+int zsort_profile_begin(void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace*& w = g_ws[(hipStream_t)stream];
+  if (!w) w = new Workspace();
+  w->prof = true;
+  w->ev_used = 0;
+  w->ev_stage.clear();
+  return ZSORT_OK;
+}
+
+int zsort_profile_end(void* stream, zsort_kernel_times* out) {
+  if (!out) return ZSORT_EINVAL;
+  std::memset(out, 0, sizeof *out);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find((hipStream_t)stream);
+  if (it == g_ws.end() || !it->second->prof) return ZSORT_EINVAL;
+  Workspace* w = it->second;
+  w->prof = false;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  for (size_t i = 0; i < w->ev_stage.size(); ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, w->ev_pool[2 * i], w->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e);
+    out->ms[w->ev_stage[i]] += ms;
+    out->launches[w->ev_stage[i]] += 1;
+  }
+  w->ev_used = 0;
+  w->ev_stage.clear();
+  return ZSORT_OK;
+}
+
 int zsort_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = ZSORT_OK;
@@ -446,6 +535,7 @@ int zsort_release(void) {
       hipError_t e = hipFree(kv.second->base);
       if (e != hipSuccess) rc = hip_fail(e);
     }
+    for (hipEvent_t ev : kv.second->ev_pool) (void)hipEventDestroy(ev);
     delete kv.second;
   }
   g_ws.clear();

@@ -25,6 +25,13 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxLevels = 40;
 constexpr int kKMax = 4096;            // largest clusters-per-pass supported
 constexpr int kLocalCap = 4096;        // largest leaf group the local sort takes
+constexpr int kWaveCap = 1024;         // largest group one wave sorts
+constexpr int kWindow = 512;           // leaf-group window; larger leaves sort alone
+constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
+
+// the kernels of a level, in launch order
+enum : int { STAGE_MOMENTS = 0, STAGE_FINALIZE = 1, STAGE_HIST = 2, STAGE_SCATTER = 3,
+             STAGE_LOCAL = 4, NSTAGES = 5 };
 
 // segment kinds, as in the recursion records
 enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3 };
@@ -43,7 +50,7 @@ struct __attribute__((aligned(16))) Seg {
   uint32_t first_work;   // first chunk's index in the level's work list
   uint32_t nchunks;
   uint32_t status_base;  // first look-back slot (segments of > 1 chunk)
-  uint32_t done;         // chunks that finished the moments pass
+  uint32_t pad1;
   int32_t parent;        // index of the parent in the previous level's list
   int32_t pad0;
   // exact moment accumulators (32-bit digit sums of x and x^2)
@@ -59,11 +66,10 @@ struct __attribute__((aligned(16))) Seg {
 };
 
 struct __attribute__((aligned(16))) Leaf {
-  uint64_t start;
+  uint32_t start;        // n < 2^31
   uint32_t count;
   uint32_t flags;        // LF_COPY: identical keys, copy only
   uint32_t src;          // 0: keys are in the caller's buffer, 1: in the alternate buffer
-  uint32_t pad[3];
 };
 
 // Control block in device memory.  Lists alternate between two slots: the
@@ -71,7 +77,8 @@ struct __attribute__((aligned(16))) Leaf {
 struct __attribute__((aligned(64))) Ctl {
   uint32_t nseg[2];
   uint32_t nwork[2];
-  uint32_t nleaf[2];
+  uint32_t nleaf[2];             // block jobs: big leaves and copies
+  uint32_t nleafw[2];            // wave jobs: groups of <= kWaveCap keys
   uint32_t nstatus[2];
   uint32_t tick[kMaxLevels];     // in-order chunk tickets of the hist pass
   uint32_t epoch;                // changes every call; tags look-back words
@@ -86,6 +93,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t n_rmap;
   uint32_t n_leafgroups;
   uint32_t max_level;
+  uint64_t local_keys;           // keys sorted or copied by the local kernel
 };
 
 enum : uint32_t { ERR_SEGCAP = 1u, ERR_WORKCAP = 2u, ERR_LEAFCAP = 4u, ERR_STATUSCAP = 8u,
@@ -120,7 +128,8 @@ struct Ws {
   void* pay[2];
   Seg* segs[2];
   uint64_t* work[2];     // (segment << 32) | chunk
-  Leaf* leaves[2];
+  Leaf* leaves[2];       // block jobs
+  Leaf* leavesw[2];      // wave jobs
   uint64_t* status;      // look-back words, [slot][k]
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
   Ctl* ctl;

@@ -202,28 +202,36 @@ __device__ __forceinline__ W8 w8_from64(uint64_t v) {
 }
 
 // round-to-nearest-even conversion: the 64 bits below the leading one, with
-// every lower bit folded into a sticky bit, then an exact power-of-two scale
-__device__ double w8_to_double(const W8& a) {
+// every lower bit folded into a sticky bit, then an exact power-of-two scale.
+// Written with constant limb indices only, so the number stays in registers.
+__device__ __forceinline__ double w8_to_double(const W8& a) {
   int top = -1;
-  for (int i = 7; i >= 0; --i)
-    if (a.d[i]) { top = i; break; }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) top = a.d[i] ? i : top;
   if (top < 0) return 0.0;
-  const int bitlen = top * 32 + (32 - __clz(a.d[top]));
-  if (bitlen <= 64) {
-    uint64_t v = ((uint64_t)a.d[1] << 32) | a.d[0];
-    return __ull2double_rn(v);
-  }
-  const int s = bitlen - 64;  // keep bits [s, s+64)
-  uint64_t w = 0;
-  for (int k = 0; k < 64; ++k) {
-    int bit = s + k;
-    uint32_t v = (a.d[bit >> 5] >> (bit & 31)) & 1u;
-    w |= (uint64_t)v << k;
-  }
+  if (top <= 1) return __ull2double_rn(((uint64_t)a.d[1] << 32) | a.d[0]);
+  uint32_t l2 = 0, l1 = 0, l0 = 0;
   bool sticky = false;
-  for (int bit = 0; bit < s; ++bit)
-    if ((a.d[bit >> 5] >> (bit & 31)) & 1u) { sticky = true; break; }
-  if (sticky) w |= 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    l2 = (i == top) ? a.d[i] : l2;
+    l1 = (i == top - 1) ? a.d[i] : l1;
+    l0 = (i == top - 2) ? a.d[i] : l0;
+    sticky = sticky || (i < top - 2 && a.d[i] != 0u);
+  }
+  // window = l2:l1:l0 (96 bits), leading one at bit 64 + (31 - clz(l2))
+  const int lz = __clz(l2);                 // 0..31
+  const uint64_t hi = ((uint64_t)l2 << 32) | l1;
+  uint64_t w;
+  if (lz == 0) {
+    w = hi;
+    sticky = sticky || (l0 != 0u);
+  } else {
+    w = (hi << lz) | ((uint64_t)l0 >> (32 - lz));
+    sticky = sticky || ((l0 << lz) != 0u);
+  }
+  if (sticky) w |= 1u;
+  const int s = 32 * (top - 2) + (32 - lz);  // bits below the 64-bit window
   return ldexp(__ull2double_rn(w), s);
 }
 
@@ -271,6 +279,38 @@ __device__ __forceinline__ void pay_store(void* p, uint64_t i, typename PayT<PW>
 }
 
 // ---------------------------------------------------------------------------
+// Visit keys x[beg, end) with the whole workgroup: 16-byte loads of key
+// pairs, UNROLL pairs in flight per thread, plus the unaligned head/tail key.
+// Order of visits is unspecified (only order-free reductions use this).
+// ---------------------------------------------------------------------------
+template <int UNROLL, typename F>
+__device__ __forceinline__ void for_each_key(const uint64_t* __restrict__ x, uint64_t beg,
+                                             uint64_t end, F&& f) {
+  const uint64_t mis = ((uintptr_t)x >> 3) & 1u;  // index i is 16-byte aligned iff (i+mis) even
+  const uint64_t a0 = beg + ((beg + mis) & 1u);
+  const uint64_t a1 = end - ((end + mis) & 1u);
+  const int t = threadIdx.x;
+  if (t == 0 && beg < a0 && beg < end) f(x[beg]);
+  if (t == 1 && a1 >= a0 && a1 < end) f(x[a1]);
+  if (a1 <= a0) return;
+  const ulonglong2* __restrict__ xp = reinterpret_cast<const ulonglong2*>(x + a0);
+  const uint64_t np = (a1 - a0) >> 1;
+  for (uint64_t p = t; p < np; p += (uint64_t)kBlock * UNROLL) {
+    ulonglong2 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint64_t q = p + (uint64_t)u * kBlock;
+      if (q < np) v[u] = xp[q];
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint64_t q = p + (uint64_t)u * kBlock;
+      if (q < np) { f(v[u].x); f(v[u].y); }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // look-back status words: tag(22) | flag(2) | value(40)
 // ---------------------------------------------------------------------------
 constexpr uint64_t kValMask = (1ull << 40) - 1;
@@ -297,7 +337,6 @@ __device__ void seg_clear_acc(Seg& s) {
   for (int i = 0; i < 8; ++i) s.acc[i] = 0;
   s.amin = ~0ull;
   s.amax = 0;
-  s.done = 0;
   s.kind = KIND_PENDING;
   s.shift = 0;
   s.o = s.M = 0;
@@ -315,13 +354,36 @@ __global__ void k_reset(Ws ws) {
   }
   if (t == 0) {
     c->epoch = c->epoch + 1u;
-    for (int s = 0; s < 2; ++s) { c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nstatus[s] = 0; }
+    for (int s = 0; s < 2; ++s) {
+      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nstatus[s] = 0;
+    }
     c->error = 0;
     c->ntrace = 0;
     c->ntrace_hist = 0;
     c->n_ident = c->n_rmap = c->n_leafgroups = 0;
     c->max_level = 0;
+    c->local_keys = 0;
   }
+}
+
+// appends a sort job for keys [start, start+count) living in buffer `src`
+// of level-slot S: groups of <= kWaveCap keys go to the wave list
+__device__ bool push_leaf(Ws& ws, int S, uint64_t start, uint32_t count, uint32_t flags,
+                          uint32_t src) {
+  Ctl* c = ws.ctl;
+  const bool small = !(flags & LF_COPY) && count <= (uint32_t)kWaveCap;
+  uint32_t* ctr = small ? &c->nleafw[S] : &c->nleaf[S];
+  const uint32_t li = atomicAdd(ctr, 1u);
+  if (li >= ws.leaf_cap) {
+    atomicOr(&c->error, ERR_LEAFCAP);
+    return false;
+  }
+  Leaf& lf = small ? ws.leavesw[S][li] : ws.leaves[S][li];
+  lf.start = (uint32_t)start;
+  lf.count = count;
+  lf.flags = flags;
+  lf.src = src;
+  return true;
 }
 
 __device__ void make_root_seg(Ws& ws, uint32_t slot_seg, uint64_t start, uint64_t count,
@@ -346,9 +408,7 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
   const uint64_t ch = (uint64_t)ws.p.chunk;
   if (n <= (uint64_t)ws.p.cutoff) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      Leaf& lf = ws.leaves[0][0];
-      lf.start = 0; lf.count = (uint32_t)n; lf.flags = 0; lf.src = 0;
-      c->nleaf[0] = 1;
+      push_leaf(ws, 0, 0, (uint32_t)n, 0u, 0u);
       c->n_leafgroups = 1;
     }
     return;
@@ -383,10 +443,7 @@ __global__ void k_init_segments(Ws ws, const int64_t* off, int32_t nseg) {
     const uint64_t a = (uint64_t)off[i], len = (uint64_t)(off[i + 1] - off[i]);
     if (len <= 1) continue;
     if (len <= (uint64_t)ws.p.cutoff) {
-      uint32_t li = atomicAdd(&c->nleaf[0], 1u);
-      if (li >= ws.leaf_cap) { atomicOr(&c->error, ERR_LEAFCAP); continue; }
-      Leaf& lf = ws.leaves[0][li];
-      lf.start = a; lf.count = (uint32_t)len; lf.flags = 0; lf.src = 0;
+      push_leaf(ws, 0, a, (uint32_t)len, 0u, 0u);
       atomicAdd(&c->n_leafgroups, 1u);
       continue;
     }
@@ -419,7 +476,7 @@ __device__ void trace_ident(Ws& ws, const Seg& s) {
   r.shift = 0; r.nonempty = 0; r.hist_off = -1;
 }
 
-__device__ __noinline__ void finalize(Ws& ws, Seg& s, int L) {
+__device__ void finalize(Ws& ws, Seg& s, int L) {
   Ctl* c = ws.ctl;
   const uint64_t cnt = s.count;
   uint64_t acc[8];
@@ -458,11 +515,11 @@ __device__ __noinline__ void finalize(Ws& ws, Seg& s, int L) {
     s.kind = KIND_IDENT;
     atomicAdd(&c->n_ident, 1u);
     trace_ident(ws, s);
-    if (L & 1) {  // keys sit in the alternate buffer: copy them home
-      uint32_t li = atomicAdd(&c->nleaf[L & 1], 1u);
-      if (li >= ws.leaf_cap) { atomicOr(&c->error, ERR_LEAFCAP); return; }
-      Leaf& lf = ws.leaves[L & 1][li];
-      lf.start = s.start; lf.count = (uint32_t)s.count; lf.flags = LF_COPY; lf.src = 1;
+    if (L & 1) {  // keys sit in the alternate buffer: copy them home, in parallel pieces
+      for (uint64_t a = 0; a < s.count; a += (uint64_t)kCopyChunk)
+        if (!push_leaf(ws, L & 1, s.start + a, (uint32_t)min((uint64_t)kCopyChunk, s.count - a),
+                       LF_COPY, 1u))
+          break;
     }
     return;
   }
@@ -514,13 +571,12 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   const int S = L & 1, N = S ^ 1;
   if (call_failed(c)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
-    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nstatus[N] = 0;
+    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nstatus[N] = 0;
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
   const uint64_t* __restrict__ x = ws.keys[S];
   const uint64_t ch = (uint64_t)ws.p.chunk;
   __shared__ uint64_t red[kWaves][10];
-  __shared__ int last;
 
   for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
     const uint64_t item = ws.work[S][w];
@@ -530,8 +586,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, b0 = 0, b1 = 0;
     uint64_t mn = ~0ull, mx = 0;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-      const uint64_t v = x[i];
+    for_each_key<4>(x, beg, end, [&](uint64_t v) {
       const uint32_t xl = (uint32_t)v, xh = (uint32_t)(v >> 32);
       const uint64_t ll = (uint64_t)xl * xl, lh = (uint64_t)xl * xh, hh = (uint64_t)xh * xh;
       a0 += (uint32_t)ll; a1 += ll >> 32;
@@ -540,7 +595,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
       b0 += xl; b1 += xh;
       mn = v < mn ? v : mn;
       mx = v > mx ? v : mx;
-    }
+    });
     uint64_t vals[10] = {a0, a1, a2, a3, a4, a5, b0, b1, mn, mx};
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -563,17 +618,19 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
         if (vals[j]) atomicAdd((unsigned long long*)&sg.acc[j], (unsigned long long)vals[j]);
       atomicMin((unsigned long long*)&sg.amin, (unsigned long long)vals[8]);
       atomicMax((unsigned long long*)&sg.amax, (unsigned long long)vals[9]);
-      __threadfence();
-      const uint32_t old = atomicAdd(&sg.done, 1u);
-      last = (old == sg.nchunks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-      __threadfence();
-      finalize(ws, sg, L);
     }
     __syncthreads();
   }
+}
+
+// finalize: one thread per segment of the level, after all its moments landed
+__global__ void __launch_bounds__(kBlock) k_finalize(Ws ws, int L) {
+  Ctl* c = ws.ctl;
+  if (call_failed(c)) return;
+  const int S = L & 1;
+  const uint32_t ns = min(c->nseg[S], ws.seg_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x)
+    finalize(ws, ws.segs[S][i], L);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,8 +739,11 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   }
   __syncthreads();
 
-  // leaf groups: a group is the leaf clusters of one run (no child between)
-  // whose starts share one window [w*cutoff, (w+1)*cutoff); < 2*cutoff keys
+  // leaf groups: consecutive leaf clusters of one run (no child cluster in
+  // between) whose starts fall in one window [w*kWindow, (w+1)*kWindow) form
+  // one group of < 2*kWindow keys; a leaf larger than kWindow is a group of
+  // its own.  Clusters are ordered (max of one < min of the next), so sorting
+  // a group as a whole equals sorting each cluster.
   int* prev = (int*)sm.t0;
   for (int b = t; b < k; b += kBlock) prev[b] = sm.h[b] ? b : -1;
   __syncthreads();
@@ -694,7 +754,9 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     if (n > cutoff) boundary = 1;
     else if (n > 0) {
       const int pb = prev[b];
-      if (pb < 0 || sm.h[pb] > cutoff || sm.bst[pb] / cutoff != sm.bst[b] / cutoff) boundary = 2;
+      if (pb < 0 || sm.h[pb] > cutoff || sm.h[pb] > (uint32_t)kWindow || n > (uint32_t)kWindow ||
+          sm.bst[pb] / (uint32_t)kWindow != sm.bst[b] / (uint32_t)kWindow)
+        boundary = 2;
     }
     sm.t1[b] = boundary;
   }
@@ -702,36 +764,44 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   for (int b = t; b < k; b += kBlock) sm.t2[b] = sm.t1[b] ? 1u : 0u;
   __syncthreads();
   const uint32_t nb = block_scan_lds(sm.t2, k, sm.sh);
-  // compacted boundaries: position and kind, reuse t0 (positions) and h? keep
-  // h intact for the trace: encode kind in the top bit of the position
+  // compacted boundaries in cluster order: start position, top bit = group start
   uint32_t* bpos = sm.t0;
   for (int b = t; b < k; b += kBlock)
     if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
   __syncthreads();
-  // count leaf groups
-  uint32_t mine = 0;
-  for (uint32_t i = t; i < nb; i += kBlock) mine += (bpos[i] >> 31);
-  uint32_t ngroups;
-  uint32_t myoff = block_excl_sum(mine, sm.sh, &ngroups);
+  uint32_t my_small = 0, my_big = 0;
+  for (uint32_t i = t; i < nb; i += kBlock) {
+    if (!(bpos[i] >> 31)) continue;
+    const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
+    const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
+    if (p1 - p0 <= (uint32_t)kWaveCap) ++my_small; else ++my_big;
+  }
+  uint32_t nsmall, nbig;
+  const uint32_t off_small = block_excl_sum(my_small, sm.sh, &nsmall);
+  const uint32_t off_big = block_excl_sum(my_big, sm.sh, &nbig);
   if (t == 0) {
-    sm.base_leaf = ngroups ? atomicAdd(&c->nleaf[S], ngroups) : 0u;
-    if (ngroups) atomicAdd(&c->n_leafgroups, ngroups);
-    if (sm.base_leaf + ngroups > ws.leaf_cap) atomicOr(&c->error, ERR_LEAFCAP);
+    sm.base_leaf = nsmall ? atomicAdd(&c->nleafw[S], nsmall) : 0u;
+    sm.base_status = nbig ? atomicAdd(&c->nleaf[S], nbig) : 0u;  // (reused as the big-list base)
+    if (nsmall + nbig) atomicAdd(&c->n_leafgroups, nsmall + nbig);
+    if (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_status + nbig > ws.leaf_cap)
+      atomicOr(&c->error, ERR_LEAFCAP);
   }
   __syncthreads();
-  if (sm.base_leaf + ngroups <= ws.leaf_cap) {
-    uint32_t o = sm.base_leaf + myoff;
+  if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_status + nbig <= ws.leaf_cap) {
+    uint32_t os = sm.base_leaf + off_small, ob = sm.base_status + off_big;
     for (uint32_t i = t; i < nb; i += kBlock) {
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
       const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
-      Leaf& lf = ws.leaves[S][o++];
-      lf.start = sg.start + p0;
+      const bool small = p1 - p0 <= (uint32_t)kWaveCap;
+      Leaf& lf = small ? ws.leavesw[S][os++] : ws.leaves[S][ob++];
+      lf.start = (uint32_t)(sg.start + p0);
       lf.count = p1 - p0;
       lf.flags = 0;
       lf.src = (uint32_t)N;  // written by this level's scatter
     }
   }
+  __syncthreads();
 
   // statistics and trace
   if (t == 0) {
@@ -794,7 +864,7 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     for (int b = t; b < k; b += kBlock) sm.h[b] = 0;
     __syncthreads();
-    for (uint64_t i = beg + t; i < end; i += kBlock) atomicAdd(&sm.h[bucket_of(x[i], mp)], 1u);
+    for_each_key<4>(x, beg, end, [&](uint64_t v) { atomicAdd(&sm.h[bucket_of(v, mp)], 1u); });
     __syncthreads();
     const uint32_t nch = sg.nchunks;
     if (nch > 1) {
@@ -841,9 +911,9 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
 template <int KMAX, int PW, int ROUNDS>
 struct ScatSmem {
   static constexpr int T = kBlock * ROUNDS;
-  uint32_t cnt[kWaves][KMAX];   // per-wave counts -> per-wave exclusive prefix
+  uint16_t cnt[kWaves][KMAX];   // per-wave counts -> per-wave exclusive prefix (<= T)
   uint32_t tst[KMAX];           // tile exclusive starts
-  uint64_t gbase[KMAX];         // running destination of each cluster
+  uint32_t gbase[KMAX];         // running destination of each cluster (n < 2^31)
   uint64_t skey[T];
   typename PayT<PW>::T spay[PW ? T : 1];
   uint16_t sbk[T];
@@ -890,7 +960,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
     for (int b = t; b < k; b += kBlock) {
       uint64_t base = sg.start + gb[b];
       if (stp) base += stp[b] & kValMask;
-      sm.gbase[b] = base;
+      sm.gbase[b] = (uint32_t)base;
     }
     for (uint64_t tb = beg; tb < end; tb += T) {
       const uint32_t tn = (uint32_t)min((uint64_t)T, end - tb);
@@ -916,7 +986,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         const uint32_t before = below(m);
         uint32_t base = 0;
         if (valid) base = sm.cnt[wv][b];
-        if (valid && before == 0) sm.cnt[wv][b] = base + (uint32_t)__popcll(m);
+        if (valid && before == 0) sm.cnt[wv][b] = (uint16_t)(base + (uint32_t)__popcll(m));
         bk[r] = b;
         rk[r] = base + before;
       }
@@ -927,7 +997,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) {
           const uint32_t v = sm.cnt[q][b];
-          sm.cnt[q][b] = run;
+          sm.cnt[q][b] = (uint16_t)run;
           run += v;
         }
         sm.tst[b] = run;
@@ -950,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
       const uint64_t seg_end = sg.start + sg.count;
       for (uint32_t p = t; p < tn; p += kBlock) {
         const uint32_t b = sm.sbk[p];
-        const uint64_t dst = sm.gbase[b] + (p - sm.tst[b]);
+        const uint64_t dst = (uint64_t)sm.gbase[b] + (p - sm.tst[b]);
         if (dst < sg.start || dst >= seg_end) {  // never taken when the counts are right
           atomicOr(&c->error, ERR_SCATTER);
           continue;
@@ -970,41 +1040,284 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
 }
 
 // ---------------------------------------------------------------------------
-// local sort: one workgroup per leaf group (< 2*cutoff <= 4096 keys), stable
-// LSD radix on the key's offset from the group minimum, 8-bit digits, only
-// as many passes as the group's range needs
+// local sort of the leaf groups.  A "team" sorts one group: a single wave for
+// groups of <= kWaveCap keys (four groups per workgroup at a time), the whole
+// workgroup for larger ones (<= kLocalCap).
+//
+// Main path, when the group's range fits in 51 bits: each key becomes the
+// unique word ((x - min) << 12) | position, so any correct sort of the words
+// is the stable sort of the keys.  Each thread sorts 16 words in registers
+// (bitonic network), then runs of 16 are merged pairwise in LDS (merge path)
+// until one run remains; the payload is gathered by position at the end.
+// Fallback (wider ranges): stable LSD radix on x - min, 8-bit digits, as many
+// passes as the range needs.
 // ---------------------------------------------------------------------------
+constexpr int kLocPer = 16;  // keys per thread
+__device__ __forceinline__ uint32_t lpad(uint32_t i) { return i + (i >> 4); }
+
+__device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
+  const bool lt = a < b;
+  const uint64_t lo = lt ? a : b, hi = lt ? b : a;
+  a = lo;
+  b = hi;
+}
+
+template <int N>
+__device__ __forceinline__ void bitonic_regs(uint64_t (&v)[N]) {
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int j = i ^ stride;
+        if (j > i) {
+          if ((i & size) == 0) cswap(v[i], v[j]);
+          else cswap(v[j], v[i]);
+        }
+      }
+}
+
+// barrier of a team of TW waves (TW == 1: LDS traffic of one wave drains in order)
+template <int TW>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TW == 1) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int PW>
 struct LocSmem {
-  static constexpr int R = kLocalCap / kBlock;  // rounds per wave (16)
+  uint64_t k[kLocalCap + kLocalCap / 16];   // packed words (padded) / radix staging
+  typename PayT<PW>::T pay[PW ? kLocalCap : 1];
   uint32_t cnt[kWaves][256];
-  uint32_t tot[256];
-  uint64_t skey[kLocalCap];
-  typename PayT<PW>::T spay[PW ? kLocalCap : 1];
+  uint32_t tot[kWaves][256];
   uint64_t rmin[kWaves], rmax[kWaves];
   uint32_t sh[kWaves + 2];
 };
 
+// team-wide exclusive sum over a[0, 256)
+template <int TW>
+__device__ __forceinline__ void team_scan256(uint32_t* a, uint32_t* sh, uint32_t tid) {
+  if constexpr (TW == kWaves) {
+    block_scan_lds(a, 256, sh);
+  } else {
+    // one wave: 4 entries per lane
+    uint32_t v0 = a[4 * tid], v1 = a[4 * tid + 1], v2 = a[4 * tid + 2], v3 = a[4 * tid + 3];
+    const uint32_t s = v0 + v1 + v2 + v3;
+    const uint32_t inc = wave_incl_sum(s);
+    uint32_t base = inc - s;
+    a[4 * tid] = base; base += v0;
+    a[4 * tid + 1] = base; base += v1;
+    a[4 * tid + 2] = base; base += v2;
+    a[4 * tid + 3] = base;
+    team_sync<1>();
+  }
+}
+
+// Sorts keys[start, start+n) of `src` into dst (and the payload alongside).
+// TW waves cooperate; tid = thread index inside the team; kb/pb = the team's
+// LDS key and payload areas (TW*1024 words + padding), cnt/tot = [TW][256]
+// and [256] counters, red = 2*TW words.
+template <int PW, int TW>
+__device__ void team_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t (*cnt)[256],
+                          uint32_t* tot, uint64_t* rmin, uint64_t* rmax, uint32_t* sh,
+                          const uint64_t* __restrict__ src, const void* psrc,
+                          uint64_t* __restrict__ dst, void* pdst, uint64_t start, uint32_t n,
+                          uint32_t tid) {
+  using P = typename PayT<PW>::T;
+  constexpr uint32_t TT = TW * kWave;  // team threads
+  const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
+
+  // blocked layout: thread tid holds positions 16*tid .. 16*tid+15
+  uint64_t key[kLocPer];
+  uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+  for (int r = 0; r < kLocPer; ++r) {
+    const uint32_t i = tid * kLocPer + r;
+    key[r] = i < n ? src[start + i] : 0ull;
+    if (i < n) { mn = key[r] < mn ? key[r] : mn; mx = key[r] > mx ? key[r] : mx; }
+  }
+  if constexpr (PW != 0)
+    for (uint32_t i = tid; i < n; i += TT) pb[i] = pay_load<PW>(psrc, start + i);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if constexpr (TW > 1) {
+    if (ln == 0) { rmin[tw] = mn; rmax[tw] = mx; }
+    team_sync<TW>();
+    mn = rmin[0]; mx = rmax[0];
+    for (int q = 1; q < TW; ++q) {
+      mn = rmin[q] < mn ? rmin[q] : mn;
+      mx = rmax[q] > mx ? rmax[q] : mx;
+    }
+  }
+  const uint64_t range = mx - mn;
+  const int bits = range ? 64 - __clzll((long long)range) : 0;
+
+  if (bits <= 51) {
+#pragma unroll
+    for (int r = 0; r < kLocPer; ++r) {
+      const uint32_t i = tid * kLocPer + r;
+      key[r] = i < n ? (((key[r] - mn) << 12) | i) : ~0ull;
+    }
+    bitonic_regs<kLocPer>(key);
+    uint32_t npad = kLocPer;
+    while (npad < n) npad <<= 1;
+    const bool active = tid * kLocPer < npad;
+    if (active)
+#pragma unroll
+      for (int r = 0; r < kLocPer; ++r) kb[lpad(tid * kLocPer + r)] = key[r];
+    team_sync<TW>();
+    for (uint32_t w = kLocPer; w < npad; w <<= 1) {
+      if (active) {
+        const uint32_t o0 = tid * kLocPer;
+        const uint32_t base = o0 & ~(2 * w - 1);
+        const uint32_t diag = o0 - base;
+        const uint32_t aB = base, bB = base + w;
+        int lo = (int)diag - (int)w;
+        lo = lo < 0 ? 0 : lo;
+        int hi = (int)(diag < w ? diag : w);
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (kb[lpad(aB + mid)] < kb[lpad(bB + diag - 1 - mid)]) lo = mid + 1;
+          else hi = mid;
+        }
+        uint32_t ai = aB + lo, bi = bB + (diag - lo);
+        const uint32_t aE = bB, bE = bB + w;
+        uint64_t a = ai < aE ? kb[lpad(ai)] : ~0ull;
+        uint64_t b = bi < bE ? kb[lpad(bi)] : ~0ull;
+#pragma unroll
+        for (int r = 0; r < kLocPer; ++r) {
+          const bool ta = a < b;
+          key[r] = ta ? a : b;
+          const uint32_t ni = (ta ? ai : bi) + 1;
+          const uint32_t lim = ta ? aE : bE;
+          const uint64_t v = ni < lim ? kb[lpad(ni)] : ~0ull;
+          ai = ta ? ni : ai;
+          bi = ta ? bi : ni;
+          a = ta ? v : a;
+          b = ta ? b : v;
+        }
+      }
+      team_sync<TW>();
+      if (active)
+#pragma unroll
+        for (int r = 0; r < kLocPer; ++r) kb[lpad(tid * kLocPer + r)] = key[r];
+      team_sync<TW>();
+    }
+    for (uint32_t i = tid; i < n; i += TT) {
+      const uint64_t v = kb[lpad(i)];
+      dst[start + i] = (v >> 12) + mn;
+      if constexpr (PW != 0) pay_store<PW>(pdst, start + i, pb[v & 4095u]);
+    }
+    team_sync<TW>();
+    return;
+  }
+
+  // wide range: stable LSD radix.  Wave-blocked layout: position
+  // tw*1024 + r*64 + ln, so ranks follow positions wave by wave, round by round.
+  P pay[kLocPer];
+#pragma unroll
+  for (int r = 0; r < kLocPer; ++r) {
+    const uint32_t i = tw * (kWave * kLocPer) + r * kWave + ln;
+    const bool valid = i < n;
+    key[r] = valid ? src[start + i] : 0ull;
+    pay[r] = valid ? pay_load<PW>(psrc, start + i) : (P)0;
+  }
+  team_sync<TW>();
+  const int passes = (bits + 7) / 8;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int sh8 = ps * 8;
+    for (int b = ln; b < 256; b += kWave) cnt[tw][b] = 0;
+    team_sync<TW>();
+    uint32_t dg[kLocPer], rk[kLocPer];
+#pragma unroll
+    for (int r = 0; r < kLocPer; ++r) {
+      const uint32_t i = tw * (kWave * kLocPer) + r * kWave + ln;
+      const bool valid = i < n;
+      const uint32_t d = valid ? (uint32_t)(((key[r] - mn) >> sh8) & 255u) : 0u;
+      const uint64_t act = __ballot(valid);
+      const uint64_t m = match_digit<8>(d, act);
+      const uint32_t before = below(m);
+      uint32_t base = 0;
+      if (valid) base = cnt[tw][d];
+      if (valid && before == 0) cnt[tw][d] = base + (uint32_t)__popcll(m);
+      dg[r] = d;
+      rk[r] = base + before;
+    }
+    team_sync<TW>();
+    for (uint32_t b = tid; b < 256; b += TT) {
+      uint32_t run = 0;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        const uint32_t v = cnt[q][b];
+        cnt[q][b] = run;
+        run += v;
+      }
+      tot[b] = run;
+    }
+    team_sync<TW>();
+    team_scan256<TW>(tot, sh, tid);
+#pragma unroll
+    for (int r = 0; r < kLocPer; ++r) {
+      const uint32_t i = tw * (kWave * kLocPer) + r * kWave + ln;
+      if (i < n) {
+        const uint32_t pos = min(tot[dg[r]] + cnt[tw][dg[r]] + rk[r], TT * kLocPer - 1);
+        kb[pos] = key[r];
+        if constexpr (PW != 0) pb[pos] = pay[r];
+      }
+    }
+    team_sync<TW>();
+#pragma unroll
+    for (int r = 0; r < kLocPer; ++r) {
+      const uint32_t i = tw * (kWave * kLocPer) + r * kWave + ln;
+      if (i < n) {
+        key[r] = kb[i];
+        if constexpr (PW != 0) pay[r] = pb[i];
+      }
+    }
+    team_sync<TW>();
+  }
+#pragma unroll
+  for (int r = 0; r < kLocPer; ++r) {
+    const uint32_t i = tw * (kWave * kLocPer) + r * kWave + ln;
+    if (i < n) {
+      dst[start + i] = key[r];
+      if constexpr (PW != 0) pay_store<PW>(pdst, start + i, pay[r]);
+    }
+  }
+  team_sync<TW>();
+}
+
 template <int PW>
 __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
-  using P = typename PayT<PW>::T;
   using Sm = LocSmem<PW>;
-  constexpr int R = Sm::R;
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
   const int S = L & 1;
   const uint32_t nl = min(c->nleaf[S], ws.leaf_cap);
+  const uint32_t nlw = min(c->nleafw[S], ws.leaf_cap);
   uint64_t* __restrict__ dst = ws.keys[0];
   void* pdst = ws.pay[0];
   const uint32_t wv = wave(), ln = lane();
   const int t = threadIdx.x;
 
+  // block jobs: copies of all-identical segments and groups of > kWaveCap keys
   for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
     const Leaf lf = ws.leaves[S][g];
     const uint64_t* __restrict__ src = ws.keys[lf.src];
     const void* psrc = ws.pay[lf.src];
     const uint32_t n = lf.count;
+    if (t == 0 && (lf.src != 0 || (!(lf.flags & LF_COPY) && n > 1)))
+      atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)n);
     if ((lf.flags & LF_COPY) || n <= 1 || n > (uint32_t)kLocalCap) {
       if (lf.src != 0)
         for (uint32_t i = t; i < n; i += kBlock) {
@@ -1015,116 +1328,67 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
         atomicOr(&c->error, ERR_LEAFCAP);
       continue;
     }
-    uint64_t key[R];
-    P pay[R];
-    uint64_t mn = ~0ull, mx = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = wv * (kWave * R) + r * kWave + ln;
-      const bool valid = i < n;
-      key[r] = valid ? src[lf.start + i] : 0ull;
-      pay[r] = valid ? pay_load<PW>(psrc, lf.start + i) : (P)0;
-      if (valid) { mn = key[r] < mn ? key[r] : mn; mx = key[r] > mx ? key[r] : mx; }
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
-      mn = a < mn ? a : mn;
-      mx = b > mx ? b : mx;
-    }
-    if (ln == 0) { sm.rmin[wv] = mn; sm.rmax[wv] = mx; }
-    __syncthreads();
-    mn = sm.rmin[0]; mx = sm.rmax[0];
-    for (int q = 1; q < kWaves; ++q) {
-      mn = sm.rmin[q] < mn ? sm.rmin[q] : mn;
-      mx = sm.rmax[q] > mx ? sm.rmax[q] : mx;
-    }
-    __syncthreads();
-    const uint64_t range = mx - mn;
-    const int bits = range ? 64 - __clzll((long long)range) : 0;
-    const int passes = (bits + 7) / 8;
-    for (int ps = 0; ps < passes; ++ps) {
-      const int sh = ps * 8;
-      for (int b = ln; b < 256; b += kWave) sm.cnt[wv][b] = 0;
-      __syncthreads();
-      uint32_t dg[R], rk[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = wv * (kWave * R) + r * kWave + ln;
-        const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)(((key[r] - mn) >> sh) & 255u) : 0u;
-        const uint64_t act = __ballot(valid);
-        const uint64_t m = match_digit<8>(d, act);
-        const uint32_t before = below(m);
-        uint32_t base = 0;
-        if (valid) base = sm.cnt[wv][d];
-        if (valid && before == 0) sm.cnt[wv][d] = base + (uint32_t)__popcll(m);
-        dg[r] = d;
-        rk[r] = base + before;
+    team_sort<PW, kWaves>(sm.k, sm.pay, sm.cnt, sm.tot[0], sm.rmin, sm.rmax, sm.sh, src, psrc, dst,
+                          pdst, lf.start, n, (uint32_t)t);
+  }
+  __syncthreads();
+  // wave jobs: groups of <= kWaveCap keys, one wave each
+  constexpr uint32_t kWaveWords = kWaveCap + kWaveCap / 16;
+  uint64_t* kb = sm.k + wv * kWaveWords;
+  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
+  for (uint32_t g = blockIdx.x * kWaves + wv; g < nlw; g += gridDim.x * kWaves) {
+    const Leaf lf = ws.leavesw[S][g];
+    const uint64_t* __restrict__ src = ws.keys[lf.src];
+    const void* psrc = ws.pay[lf.src];
+    const uint32_t n = lf.count;
+    if (ln == 0 && (lf.src != 0 || n > 1))
+      atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)n);
+    if (n <= 1) {
+      if (lf.src != 0 && ln == 0 && n == 1) {
+        dst[lf.start] = src[lf.start];
+        if constexpr (PW != 0) pay_store<PW>(pdst, lf.start, pay_load<PW>(psrc, lf.start));
       }
-      __syncthreads();
-      {
-        const int b = t;  // 256 digits, one per thread
-        uint32_t run = 0;
-#pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
-          const uint32_t v = sm.cnt[q][b];
-          sm.cnt[q][b] = run;
-          run += v;
-        }
-        sm.tot[b] = run;
-      }
-      __syncthreads();
-      block_scan_lds(sm.tot, 256, sm.sh);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = wv * (kWave * R) + r * kWave + ln;
-        if (i < n) {
-          const uint32_t pos = min(sm.tot[dg[r]] + sm.cnt[wv][dg[r]] + rk[r], (uint32_t)kLocalCap - 1);
-          sm.skey[pos] = key[r];
-          if constexpr (PW != 0) sm.spay[pos] = pay[r];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = wv * (kWave * R) + r * kWave + ln;
-        if (i < n) {
-          key[r] = sm.skey[i];
-          if constexpr (PW != 0) pay[r] = sm.spay[i];
-        }
-      }
-      __syncthreads();
+      continue;
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = wv * (kWave * R) + r * kWave + ln;
-      if (i < n) {
-        dst[lf.start + i] = key[r];
-        if constexpr (PW != 0) pay_store<PW>(pdst, lf.start + i, pay[r]);
-      }
-    }
-    __syncthreads();
+    team_sort<PW, 1>(kb, pb, &sm.cnt[wv], sm.tot[wv], nullptr, nullptr, nullptr, src, psrc, dst,
+                     pdst, lf.start, n, ln);
   }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-struct Grids {
-  int moments, hist, scatter, local;
-};
+template <int KMAX, int KBITS, int PW, int ROUNDS>
+static const void* stage_fn(int stage) {
+  switch (stage) {
+    case STAGE_MOMENTS: return (const void*)k_moments;
+    case STAGE_FINALIZE: return (const void*)k_finalize;
+    case STAGE_HIST: return (const void*)k_hist<KMAX>;
+    case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS>;
+    default: return (const void*)k_local<PW>;
+  }
+}
 
 template <int KMAX, int KBITS, int PW, int ROUNDS>
-static hipError_t launch_levels_t(const Ws& ws, int levels, const Grids& g, bool with_local,
-                                  hipStream_t st) {
-  for (int L = 0; L < levels; ++L) {
-    hipLaunchKernelGGL(k_moments, dim3(g.moments), dim3(kBlock), 0, st, ws, L);
-    hipLaunchKernelGGL((k_hist<KMAX>), dim3(g.hist), dim3(kBlock), 0, st, ws, L);
-    hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(g.scatter), dim3(kBlock), 0, st, ws, L);
-    if (with_local) hipLaunchKernelGGL((k_local<PW>), dim3(g.local), dim3(kBlock), 0, st, ws, L);
+static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t st) {
+  switch (stage) {
+    case STAGE_MOMENTS:
+      hipLaunchKernelGGL(k_moments, dim3(grid), dim3(kBlock), 0, st, ws, L);
+      break;
+    case STAGE_FINALIZE:
+      hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, st, ws, L);
+      break;
+    case STAGE_HIST:
+      hipLaunchKernelGGL((k_hist<KMAX>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      break;
+    case STAGE_SCATTER:
+      hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(grid), dim3(kBlock), 0, st, ws,
+                         L);
+      break;
+    default:
+      hipLaunchKernelGGL((k_local<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      break;
   }
-  return hipGetLastError();
 }
 
 }  // namespace zs
@@ -1150,20 +1414,43 @@ hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, 
   return hipGetLastError();
 }
 
-hipError_t launch_levels(const Ws& ws, int levels, int grid, bool with_local, hipStream_t st) {
-  Grids g{grid, grid, grid, grid};
+#define ZS_DISPATCH(KM, KB, CALL)                     \
+  if (k <= KM) {                                      \
+    if (pw == 0) CALL(KM, KB, 0);                      \
+    else if (pw == 4) CALL(KM, KB, 4);                 \
+    else CALL(KM, KB, 8);                              \
+  }
+
+hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st) {
   const int k = ws.p.k;
   const int pw = ws.p.pw;
-#define ZS_DISPATCH(KM, KB)                                                                \
-  if (k <= KM) {                                                                           \
-    if (pw == 0) return launch_levels_t<KM, KB, 0, 8>(ws, levels, g, with_local, st);     \
-    if (pw == 4) return launch_levels_t<KM, KB, 4, 8>(ws, levels, g, with_local, st);     \
-    return launch_levels_t<KM, KB, 8, 8>(ws, levels, g, with_local, st);                   \
-  }
-  ZS_DISPATCH(1024, 10)
-  ZS_DISPATCH(4096, 12)
-#undef ZS_DISPATCH
+#define ZS_LAUNCH(KM, KB, PWV)                                   \
+  do {                                                           \
+    launch_stage_t<KM, KB, PWV, 8>(ws, L, stage, grid, st);      \
+    return hipGetLastError();                                    \
+  } while (0)
+  ZS_DISPATCH(1024, 10, ZS_LAUNCH)
+  ZS_DISPATCH(4096, 12, ZS_LAUNCH)
+#undef ZS_LAUNCH
   return hipErrorInvalidValue;
 }
+
+// resident workgroups per compute unit of a stage's kernel (at least 1)
+int stage_blocks_per_cu(int k, int pw, int stage) {
+  const void* fn = nullptr;
+#define ZS_FN(KM, KB, PWV)                                       \
+  do {                                                           \
+    fn = stage_fn<KM, KB, PWV, 8>(stage);                        \
+  } while (0)
+  ZS_DISPATCH(1024, 10, ZS_FN)
+  else ZS_DISPATCH(4096, 12, ZS_FN)
+#undef ZS_FN
+  if (!fn) return 1;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
+    return 1;
+  return nb;
+}
+#undef ZS_DISPATCH
 
 }  // namespace zs
