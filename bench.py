@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GKeys/s + % HBM peak, stable 1e8 u64+idx: z-score vs learned-CDF vs batched"
 HBM_PEAK_GBS = 8000.0
-STAGES = ("moments", "finalize", "hist", "scatter", "local")
+STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
 PRIMARY = dict(workload="lognormal", n=10**8, payload_bytes=8,
                desc="plain z-score path, 1e8 u64 keys floor(exp(N(40, 2.5^2))) clamped, "
                     "u64 index payload")
@@ -60,7 +60,7 @@ def stage_bytes(stats: dict, pw: int) -> dict:
     mk = sum(stats["mkeys_per_level"])
     dk = sum(stats["keys_per_level"])
     return {"moments": 8.0 * mk, "finalize": 0.0, "hist": 8.0 * dk, "scatter": 2.0 * kp * dk,
-            "local": 2.0 * kp * stats["local_keys"]}
+            "local": 2.0 * kp * stats["local_keys"], "local_hard": 0.0}
 
 
 def to_device(keys_np, pay_np, dev):
@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=PRIMARY["n"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -189,6 +191,14 @@ def main():
     cfg = dict(DEFAULT_CFG)
     spec = dict(PRIMARY, n=args.n)
 
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.int64, device=dev).fill_(7)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy probe: 3 x 1 GiB device-to-device copies")
     keys, ms, stats, kt = run_workload(spec, args.steps, args.warmup, cfg, dev)
     pw = spec["payload_bytes"]
     n = spec["n"]

@@ -61,14 +61,17 @@ enum {
  *   max_zlevels  depth at which the z-score map gives way to the exact range
  *                map, 0..16 (0 = range map everywhere).  Default 8.
  *   chunk        keys per work item of a pass, a multiple of 2048 in
- *                [2048, 2^20].  Default 16384.
+ *                [2048, 2^20] (and of tile).  Default 16384.
+ *   tile         keys a workgroup stages through LDS per step of the stable
+ *                scatter: 2048 or 4096 (4096 needs k <= 1024).  Default 2048.
  */
 typedef struct zsort_config {
   int32_t k;
   int32_t cutoff;
   int32_t max_zlevels;
   int32_t chunk;
-  int32_t reserved[4];
+  int32_t tile;
+  int32_t reserved[3];
 } zsort_config;
 
 /* Fills cfg with the defaults above.  Returns ZSORT_OK or ZSORT_EINVAL (null). */
@@ -192,13 +195,13 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
  * `stream` is bracketed by a pair of hipEvents recorded on that same stream;
  * _end synchronises the stream and sums the elapsed times per kernel kind:
  * index 0 moments, 1 finalize (statistics of the map), 2 histogram (with
- * look-back and classification), 3 stable scatter, 4 local sort.
- * launches[i] counts the launches, including those of levels that found no
- * work.
+ * look-back and classification), 3 stable scatter, 4 local sort (bucket
+ * pass), 5 local sort fallback (merge / radix).  launches[i] counts the
+ * launches, including those of levels that found no work.
  */
 typedef struct zsort_kernel_times {
-  double ms[5];
-  uint64_t launches[5];
+  double ms[6];
+  uint64_t launches[6];
 } zsort_kernel_times;
 
 int zsort_profile_begin(void* stream);

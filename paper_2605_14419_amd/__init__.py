@@ -25,13 +25,13 @@ EXPORTED = [
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
     "zsort_strerror", "zsort_profile_begin", "zsort_profile_end",
 ]
-STAGES = ("moments", "finalize", "hist", "scatter", "local")
+STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
 
 
 class ZsortConfig(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("max_zlevels", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class ZsortStats(ctypes.Structure):
@@ -47,7 +47,7 @@ class ZsortStats(ctypes.Structure):
 
 
 class ZsortKernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_uint64 * 5)]
+    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_uint64 * 6)]
 
 
 TRACE_REC = np.dtype([
@@ -233,7 +233,7 @@ def zsort_profile_begin(stream=None):
 
 
 def zsort_profile_end(stream=None) -> dict:
-    """{stage: (total ms, launches)} for moments / finalize / hist / scatter / local."""
+    """{stage: (total ms, launches)} for every kernel kind of a level."""
     t = ZsortKernelTimes()
     _check("zsort_profile_end", lib().zsort_profile_end(_stream(stream), ctypes.byref(t)))
     return {name: (t.ms[i], int(t.launches[i])) for i, name in enumerate(STAGES)}

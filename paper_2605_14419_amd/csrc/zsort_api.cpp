@@ -19,7 +19,7 @@ hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st);
 hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, uint64_t n,
                                 hipStream_t st);
 hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st);
-int stage_blocks_per_cu(int k, int pw, int stage);
+int stage_blocks_per_cu(int k, int pw, int tile, int stage);
 }  // namespace zs
 
 namespace {
@@ -28,18 +28,20 @@ using zs::Ws;
 
 struct Shape {
   uint64_t n = 0;
-  int pw = 0, k = 0, cutoff = 0, chunk = 0;
+  int pw = 0, k = 0, cutoff = 0, chunk = 0, tile = 0;
   int64_t nseg = 0;
   int64_t trace_cap = 0, trace_hist_cap = 0;
   bool operator==(const Shape& o) const {
     return n == o.n && pw == o.pw && k == o.k && cutoff == o.cutoff && chunk == o.chunk &&
+           tile == o.tile &&
            nseg == o.nseg && trace_cap == o.trace_cap && trace_hist_cap == o.trace_hist_cap;
   }
 };
 
 struct Layout {
   size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
-      off_status,
+      off_hard[2],
+      off_status, off_part,
       off_bstart, off_trace, off_thist, total;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap;
 };
@@ -75,8 +77,10 @@ Layout plan(const Shape& s) {
     L.off_work[i] = take(work_cap * 8);
     L.off_leaves[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_leavesw[i] = take(leaf_cap * sizeof(zs::Leaf));
+    L.off_hard[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
   L.off_status = take(status_cap * (size_t)s.k * 8);
+  L.off_part = take(work_cap * 10 * 8);
   L.off_bstart = take(seg_cap * (size_t)s.k * 4);
   L.off_trace = take((size_t)s.trace_cap * sizeof(zs::TraceRec));
   L.off_thist = take((size_t)s.trace_hist_cap * 4);
@@ -98,6 +102,11 @@ struct Workspace {
   bool has_last = false;
   // per-kernel event timing (zsort_profile_begin / _end)
   bool prof = false;
+  // pacing of level launches: per level, a host copy of the next level's
+  // segment count and an event recorded after the level's kernels
+  uint32_t* h_nseg = nullptr;  // pinned, kMaxLevels + 1 words
+  hipEvent_t lvl_ev[zs::kMaxLevels] = {};
+  bool lvl_ev_ok = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_stage;  // stage of each (start, end) pair
@@ -146,9 +155,11 @@ bool capturing(hipStream_t st) {
 
 int check_cfg(const zsort_config* c) {
   if (c->k < 16 || c->k > zs::kKMax) return ZSORT_EINVAL;
-  if (c->cutoff < 1 || c->cutoff > zs::kLocalCap / 2) return ZSORT_EINVAL;
+  if (c->cutoff < 1 || c->cutoff > zs::kBlockCap) return ZSORT_EINVAL;
   if (c->max_zlevels < 0 || c->max_zlevels > 16) return ZSORT_EINVAL;
   if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
+  if (c->tile != 2048 && c->tile != 4096) return ZSORT_EINVAL;
+  if (c->tile == 4096 && (c->k > 1024 || c->chunk % 4096)) return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 
@@ -225,8 +236,10 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
     ws.work[i] = (uint64_t*)(w->base + L.off_work[i]);
     ws.leaves[i] = (zs::Leaf*)(w->base + L.off_leaves[i]);
     ws.leavesw[i] = (zs::Leaf*)(w->base + L.off_leavesw[i]);
+    ws.hard[i] = (zs::Leaf*)(w->base + L.off_hard[i]);
   }
   ws.status = (uint64_t*)(w->base + L.off_status);
+  ws.part = (uint64_t*)(w->base + L.off_part);
   ws.bstart = (uint32_t*)(w->base + L.off_bstart);
   ws.ctl = (zs::Ctl*)(w->base + L.off_ctl);
   ws.trace = w->shape.trace_cap ? (zs::TraceRec*)(w->base + L.off_trace) : nullptr;
@@ -242,22 +255,24 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
   ws.p.cutoff = c.cutoff;
   ws.p.max_zlevels = c.max_zlevels;
   ws.p.chunk = c.chunk;
+  ws.p.tile = c.tile;
   ws.p.pw = pw;
   return ws;
 }
 
 // grid of a stage: every compute unit filled to the kernel's occupancy
-int grid_size(int k, int pw, int stage) {
+int grid_size(int k, int pw, int tile, int stage) {
   static std::mutex mu;
   static std::unordered_map<int, int> cache;
-  const int key = (k > 1024 ? 1 : 0) | (pw << 1) | (stage << 8);
+  const int kc = k <= 256 ? 0 : (k <= 512 ? 1 : (k <= 1024 ? 2 : 3));
+  const int key = kc | (pw << 2) | ((tile == 4096) << 6) | (stage << 8);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   int per = 0;
   if (it != cache.end()) {
     per = it->second;
   } else {
-    per = std::min(8, zs::stage_blocks_per_cu(k, pw, stage));
+    per = std::min(8, zs::stage_blocks_per_cu(k, pw, tile, stage));
     cache[key] = per;
   }
   if (stage == zs::STAGE_FINALIZE) return std::max(1, g_cu_count);
@@ -276,6 +291,23 @@ struct Call {
   bool level0_only;
 };
 
+// pinned count buffer and per-level events, created once per workspace
+bool pacing_ready(Workspace* w) {
+  if (w->lvl_ev_ok) return true;
+  if (!w->h_nseg) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, (zs::kMaxLevels + 1) * sizeof(uint32_t), hipHostMallocDefault) !=
+        hipSuccess)
+      return false;
+    w->h_nseg = (uint32_t*)p;
+  }
+  for (int i = 0; i < zs::kMaxLevels; ++i)
+    if (!w->lvl_ev[i] && hipEventCreateWithFlags(&w->lvl_ev[i], hipEventDisableTiming) != hipSuccess)
+      return false;
+  w->lvl_ev_ok = true;
+  return true;
+}
+
 int run(const Call& c, hipStream_t st, Workspace** wout) {
   Shape s;
   s.n = c.n;
@@ -283,6 +315,7 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   s.k = c.cfg.k;
   s.cutoff = c.cfg.cutoff;
   s.chunk = c.cfg.chunk;
+  s.tile = c.cfg.tile;
   s.nseg = c.off ? c.nseg : 0;
   s.trace_cap = c.trace_cap;
   s.trace_hist_cap = c.hist_cap;
@@ -296,10 +329,26 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
     else e = zs::launch_init_single(ws, c.n, st);
   }
   const int levels = c.level0_only ? 1 : levels_for(c.cfg);
+  // Pacing: level L >= 2 is launched only if level L-1 holds segments, which
+  // the host learns from a copy of the count taken after level L-2.  The host
+  // waits for level L-2 while level L-1 runs, so one level is always queued
+  // ahead of the device.  Under stream capture every level is launched (each
+  // kernel of an empty level exits at once).
+  const bool paced = !c.level0_only && !capturing(st) && pacing_ready(w);
   for (int L = 0; L < levels && e == hipSuccess; ++L) {
+    if (paced && L >= 2) {
+      e = hipEventSynchronize(w->lvl_ev[L - 2]);
+      if (e != hipSuccess) break;
+      if (w->h_nseg[L - 1] == 0) break;
+    }
     for (int sid = 0; sid < zs::NSTAGES && e == hipSuccess; ++sid) {
-      if (c.level0_only && sid == zs::STAGE_LOCAL) continue;
-      e = stage(w, ws, L, sid, grid_size(c.cfg.k, c.pw, sid), st);
+      if (c.level0_only && (sid == zs::STAGE_LOCAL || sid == zs::STAGE_LOCAL_HARD)) continue;
+      e = stage(w, ws, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
+    }
+    if (paced && e == hipSuccess) {
+      e = hipMemcpyAsync(&w->h_nseg[L + 1], &ws.ctl->nseg[(L + 1) & 1], sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[L], st);
     }
   }
   if (e != hipSuccess) return hip_fail(e);
@@ -336,6 +385,7 @@ int zsort_default_config(zsort_config* cfg) {
   cfg->cutoff = 2048;
   cfg->max_zlevels = 8;
   cfg->chunk = 16384;
+  cfg->tile = 2048;
   return ZSORT_OK;
 }
 
@@ -536,6 +586,9 @@ int zsort_release(void) {
       if (e != hipSuccess) rc = hip_fail(e);
     }
     for (hipEvent_t ev : kv.second->ev_pool) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : kv.second->lvl_ev)
+      if (ev) (void)hipEventDestroy(ev);
+    if (kv.second->h_nseg) (void)hipHostFree(kv.second->h_nseg);
     delete kv.second;
   }
   g_ws.clear();

@@ -24,14 +24,15 @@ constexpr int kBlock = 256;            // threads per workgroup, 4 waves
 constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxLevels = 40;
 constexpr int kKMax = 4096;            // largest clusters-per-pass supported
-constexpr int kLocalCap = 4096;        // largest leaf group the local sort takes
-constexpr int kWaveCap = 1024;         // largest group one wave sorts
-constexpr int kWindow = 512;           // leaf-group window; larger leaves sort alone
+constexpr int kLocalCap = 4096;        // largest group the fallback local sort takes
+constexpr int kBlockCap = 2048;        // largest group (= largest cutoff) of the fast local sort
+constexpr int kWaveCap = 512;          // largest group one wave sorts
+constexpr int kWindow = 256;           // leaf-group window; larger leaves sort alone
 constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
 
 // the kernels of a level, in launch order
 enum : int { STAGE_MOMENTS = 0, STAGE_FINALIZE = 1, STAGE_HIST = 2, STAGE_SCATTER = 3,
-             STAGE_LOCAL = 4, NSTAGES = 5 };
+             STAGE_LOCAL = 4, STAGE_LOCAL_HARD = 5, NSTAGES = 6 };
 
 // segment kinds, as in the recursion records
 enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3 };
@@ -53,9 +54,6 @@ struct __attribute__((aligned(16))) Seg {
   uint32_t pad1;
   int32_t parent;        // index of the parent in the previous level's list
   int32_t pad0;
-  // exact moment accumulators (32-bit digit sums of x and x^2)
-  uint64_t acc[8];
-  uint64_t amin, amax;
   // results of finalize
   uint64_t o, M;
   uint64_t s1[2];        // sum (x - o)
@@ -79,6 +77,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nwork[2];
   uint32_t nleaf[2];             // block jobs: big leaves and copies
   uint32_t nleafw[2];            // wave jobs: groups of <= kWaveCap keys
+  uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
   uint32_t tick[kMaxLevels];     // in-order chunk tickets of the hist pass
   uint32_t epoch;                // changes every call; tags look-back words
@@ -119,6 +118,7 @@ struct Params {
   int32_t cutoff;        // leaf size
   int32_t max_zlevels;
   int32_t chunk;         // keys per work item
+  int32_t tile;          // keys per scatter tile (2048 or 4096)
   int32_t pw;            // payload bytes: 0, 4, 8
 };
 
@@ -130,7 +130,9 @@ struct Ws {
   uint64_t* work[2];     // (segment << 32) | chunk
   Leaf* leaves[2];       // block jobs
   Leaf* leavesw[2];      // wave jobs
+  Leaf* hard[2];         // jobs for the fallback local sort
   uint64_t* status;      // look-back words, [slot][k]
+  uint64_t* part;        // per work item: 8 digit sums, min, max (moments pass)
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
   Ctl* ctl;
   TraceRec* trace;       // may be null

@@ -334,9 +334,6 @@ __device__ __forceinline__ void st_publish(uint64_t* p, uint32_t tag, uint32_t f
 // reset + level-0 set-up
 // ---------------------------------------------------------------------------
 __device__ void seg_clear_acc(Seg& s) {
-  for (int i = 0; i < 8; ++i) s.acc[i] = 0;
-  s.amin = ~0ull;
-  s.amax = 0;
   s.kind = KIND_PENDING;
   s.shift = 0;
   s.o = s.M = 0;
@@ -355,7 +352,8 @@ __global__ void k_reset(Ws ws) {
   if (t == 0) {
     c->epoch = c->epoch + 1u;
     for (int s = 0; s < 2; ++s) {
-      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nstatus[s] = 0;
+      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nhard[s] = 0;
+      c->nstatus[s] = 0;
     }
     c->error = 0;
     c->ntrace = 0;
@@ -476,14 +474,12 @@ __device__ void trace_ident(Ws& ws, const Seg& s) {
   r.shift = 0; r.nonempty = 0; r.hist_off = -1;
 }
 
-__device__ void finalize(Ws& ws, Seg& s, int L) {
+// acc: the segment's 32-bit digit sums a0..a5 (of x^2), b0, b1 (of x), then min, max
+__device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10]) {
   Ctl* c = ws.ctl;
   const uint64_t cnt = s.count;
-  uint64_t acc[8];
-  for (int i = 0; i < 8; ++i)
-    acc[i] = __hip_atomic_load(&s.acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t o = __hip_atomic_load(&s.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t M = __hip_atomic_load(&s.amax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t o = acc[8];
+  const uint64_t M = acc[9];
   s.o = o;
   s.M = M;
   atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)cnt);
@@ -571,7 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   const int S = L & 1, N = S ^ 1;
   if (call_failed(c)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
-    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nstatus[N] = 0;
+    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nhard[N] = 0;
+    c->nstatus[N] = 0;
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
   const uint64_t* __restrict__ x = ws.keys[S];
@@ -597,6 +594,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
       mx = v > mx ? v : mx;
     });
     uint64_t vals[10] = {a0, a1, a2, a3, a4, a5, b0, b1, mn, mx};
+    (void)sg;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
 #pragma unroll
@@ -608,29 +606,58 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
     if (lane() == 0)
       for (int j = 0; j < 10; ++j) red[wave()][j] = vals[j];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 10) {  // this chunk's partial moments, reduced later per segment
+      const int j = threadIdx.x;
+      uint64_t v = red[0][j];
       for (int wv = 1; wv < kWaves; ++wv) {
-        for (int j = 0; j < 8; ++j) vals[j] += red[wv][j];
-        vals[8] = red[wv][8] < vals[8] ? red[wv][8] : vals[8];
-        vals[9] = red[wv][9] > vals[9] ? red[wv][9] : vals[9];
+        const uint64_t q = red[wv][j];
+        v = j < 8 ? v + q : (j == 8 ? (q < v ? q : v) : (q > v ? q : v));
       }
-      for (int j = 0; j < 8; ++j)
-        if (vals[j]) atomicAdd((unsigned long long*)&sg.acc[j], (unsigned long long)vals[j]);
-      atomicMin((unsigned long long*)&sg.amin, (unsigned long long)vals[8]);
-      atomicMax((unsigned long long*)&sg.amax, (unsigned long long)vals[9]);
+      ws.part[(uint64_t)w * 10 + j] = v;
     }
     __syncthreads();
   }
 }
 
-// finalize: one thread per segment of the level, after all its moments landed
+// finalize: one workgroup per segment sums the partial moments of its chunks
+// (exact, order-free integer sums), then one thread derives the statistics
 __global__ void __launch_bounds__(kBlock) k_finalize(Ws ws, int L) {
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
   const int S = L & 1;
   const uint32_t ns = min(c->nseg[S], ws.seg_cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x)
-    finalize(ws, ws.segs[S][i], L);
+  __shared__ uint64_t red[kWaves][10];
+  for (uint32_t i = blockIdx.x; i < ns; i += gridDim.x) {
+    Seg& sg = ws.segs[S][i];
+    uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
+    for (uint32_t q = threadIdx.x; q < sg.nchunks; q += kBlock) {
+      const uint64_t* pr = ws.part + (uint64_t)(sg.first_work + q) * 10;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] += pr[j];
+      v[8] = pr[8] < v[8] ? pr[8] : v[8];
+      v[9] = pr[9] > v[9] ? pr[9] : v[9];
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] += __shfl_xor(v[j], o);
+      const uint64_t a = __shfl_xor(v[8], o), b = __shfl_xor(v[9], o);
+      v[8] = a < v[8] ? a : v[8];
+      v[9] = b > v[9] ? b : v[9];
+    }
+    if (lane() == 0)
+      for (int j = 0; j < 10; ++j) red[wave()][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int wv = 1; wv < kWaves; ++wv) {
+        for (int j = 0; j < 8; ++j) v[j] += red[wv][j];
+        v[8] = red[wv][8] < v[8] ? red[wv][8] : v[8];
+        v[9] = red[wv][9] > v[9] ? red[wv][9] : v[9];
+      }
+      finalize(ws, sg, L, v);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -914,8 +941,7 @@ struct ScatSmem {
   uint16_t cnt[kWaves][KMAX];   // per-wave counts -> per-wave exclusive prefix (<= T)
   uint32_t tst[KMAX];           // tile exclusive starts
   uint32_t gbase[KMAX];         // running destination of each cluster (n < 2^31)
-  uint64_t skey[T];
-  typename PayT<PW>::T spay[PW ? T : 1];
+  uint64_t stage[T];            // keys in cluster order, then the payloads
   uint16_t sbk[T];
   uint32_t sh[kWaves + 2];
 };
@@ -1004,15 +1030,17 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
       }
       __syncthreads();
       block_scan_lds(sm.tst, k, sm.sh);
-      // stage in cluster order
+      // stage the keys in cluster order, write them, then the same for payloads
+      uint32_t posr[ROUNDS];
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
+        posr[r] = 0;
         if (i < tn) {
           const uint32_t b = bk[r];
           const uint32_t pos = min(sm.tst[b] + sm.cnt[wv][b] + rk[r], (uint32_t)T - 1);
-          sm.skey[pos] = key[r];
-          if constexpr (PW != 0) sm.spay[pos] = pay[r];
+          posr[r] = pos;
+          sm.stage[pos] = key[r];
           sm.sbk[pos] = (uint16_t)b;
         }
       }
@@ -1025,8 +1053,24 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
           atomicOr(&c->error, ERR_SCATTER);
           continue;
         }
-        xout[dst] = sm.skey[p];
-        if constexpr (PW != 0) pay_store<PW>(pout, dst, sm.spay[p]);
+        xout[dst] = sm.stage[p];
+      }
+      if constexpr (PW != 0) {
+        using P2 = typename PayT<PW>::T;
+        P2* spay = reinterpret_cast<P2*>(sm.stage);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+          const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
+          if (i < tn) spay[posr[r]] = pay[r];
+        }
+        __syncthreads();
+        for (uint32_t p = t; p < tn; p += kBlock) {
+          const uint32_t b = sm.sbk[p];
+          const uint64_t dst = (uint64_t)sm.gbase[b] + (p - sm.tst[b]);
+          if (dst < sg.start || dst >= seg_end) continue;
+          pay_store<PW>(pout, dst, spay[p]);
+        }
       }
       __syncthreads();
       // advance the running destinations by this tile's counts
@@ -1297,8 +1341,227 @@ __device__ void team_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t (*cnt
 }
 
 template <int PW>
-__global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
+__global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
   using Sm = LocSmem<PW>;
+  __shared__ Sm sm;
+  Ctl* c = ws.ctl;
+  if (call_failed(c)) return;
+  const int S = L & 1;
+  const uint32_t nh = min(c->nhard[S], ws.leaf_cap);
+  uint64_t* __restrict__ dst = ws.keys[0];
+  void* pdst = ws.pay[0];
+  const uint32_t wv = wave(), ln = lane();
+  const int t = threadIdx.x;
+  // groups of > kWaveCap keys: the whole workgroup
+  for (uint32_t g = blockIdx.x; g < nh; g += gridDim.x) {
+    const Leaf lf = ws.hard[S][g];
+    if (lf.count <= (uint32_t)kWaveCap) continue;
+    team_sort<PW, kWaves>(sm.k, sm.pay, sm.cnt, sm.tot[0], sm.rmin, sm.rmax, sm.sh,
+                          ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count,
+                          (uint32_t)t);
+  }
+  __syncthreads();
+  // groups of <= kWaveCap keys: one wave each
+  constexpr uint32_t kWaveWords = kWaveCap + kWaveCap / 16;
+  uint64_t* kb = sm.k + wv * kWaveWords;
+  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
+  for (uint32_t g = blockIdx.x * kWaves + wv; g < nh; g += gridDim.x * kWaves) {
+    const Leaf lf = ws.hard[S][g];
+    if (lf.count > (uint32_t)kWaveCap) continue;
+    team_sort<PW, 1>(kb, pb, &sm.cnt[wv], sm.tot[wv], nullptr, nullptr, nullptr,
+                     ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count, ln);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fast local sort: one counting pass on the top bits of x - min (about one
+// bucket per key), then a tiny insertion sort inside each bucket.  Works on
+// the unique words ((x - min) << 12) | position, so the result is the stable
+// sort.  Returns false, before writing anything, if the group's range needs
+// more than 51 bits or some bucket holds more than kBucketMax keys; such
+// groups go to the fallback sort.
+// ---------------------------------------------------------------------------
+constexpr int kBucketMax = 16;
+
+template <int PW>
+struct FastSmem {
+  uint64_t k[kBlockCap];                        // words in bucket order
+  typename PayT<PW>::T pay[PW ? kBlockCap : 1]; // payload by input position
+  uint32_t cnt[kBlockCap / 2];                  // 16-bit bucket counters, two per word
+  uint64_t rmin[kWaves], rmax[kWaves];
+  uint32_t sh[kWaves + 2];
+};
+
+__device__ __forceinline__ uint32_t c16_get(const uint32_t* c, uint32_t b) {
+  return (c[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
+}
+
+template <int PW, int TW, int R>
+__device__ bool fast_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt, uint64_t* rmin,
+                          uint64_t* rmax, uint32_t* sh, const uint64_t* __restrict__ src,
+                          const void* psrc, uint64_t* __restrict__ dst, void* pdst,
+                          uint64_t start, uint32_t n, uint32_t tid) {
+  using P = typename PayT<PW>::T;
+  constexpr uint32_t TT = TW * kWave;  // n <= TT * R
+  const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
+  uint64_t key[R];
+  uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * TT + tid;
+    const bool valid = i < n;
+    key[r] = valid ? src[start + i] : 0ull;
+    if (valid) {
+      mn = key[r] < mn ? key[r] : mn;
+      mx = key[r] > mx ? key[r] : mx;
+      if constexpr (PW != 0) pb[i] = pay_load<PW>(psrc, start + i);
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if constexpr (TW > 1) {
+    if (ln == 0) { rmin[tw] = mn; rmax[tw] = mx; }
+    team_sync<TW>();
+    mn = rmin[0]; mx = rmax[0];
+#pragma unroll
+    for (int q = 1; q < TW; ++q) {
+      mn = rmin[q] < mn ? rmin[q] : mn;
+      mx = rmax[q] > mx ? rmax[q] : mx;
+    }
+  }
+  const uint64_t range = mx - mn;
+  const int bits = range ? 64 - __clzll((long long)range) : 0;
+  if (bits == 0) {  // all keys equal: input order is the stable order
+    if (src != dst)
+      for (uint32_t i = tid; i < n; i += TT) {
+        dst[start + i] = src[start + i];
+        if constexpr (PW != 0) pay_store<PW>(pdst, start + i, pay_load<PW>(psrc, start + i));
+      }
+    team_sync<TW>();
+    return true;
+  }
+  if (bits > 51) {
+    team_sync<TW>();
+    return false;
+  }
+  uint32_t nb = 64;
+  while (nb < n) nb <<= 1;
+  int d = 6;
+  while ((1u << d) < nb) ++d;
+  const int shb = bits > d ? bits - d : 0;
+  for (uint32_t i = tid; i < nb / 2; i += TT) cnt[i] = 0;
+  team_sync<TW>();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * TT + tid;
+    if (i < n) {
+      const uint32_t b = (uint32_t)((key[r] - mn) >> shb);
+      atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) * 16u));
+    }
+  }
+  team_sync<TW>();
+  // exclusive scan of the counters; each thread owns nb/TT consecutive ones
+  const uint32_t per = (nb + TT - 1) / TT;  // even, >= 1 ... counters per thread
+  const uint32_t b0 = tid * per;
+  uint32_t tsum = 0, tmax = 0;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint32_t b = b0 + j;
+    if (b < nb) {
+      const uint32_t v = c16_get(cnt, b);
+      tsum += v;
+      tmax = v > tmax ? v : tmax;
+    }
+  }
+  uint32_t base;
+  uint32_t gmax = tmax;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, o));
+  if constexpr (TW == 1) {
+    base = wave_incl_sum(tsum) - tsum;
+  } else {
+    if (ln == 0) sh[tw] = gmax;
+    team_sync<TW>();
+    for (int q = 0; q < TW; ++q) gmax = max(gmax, sh[q]);
+    team_sync<TW>();
+    uint32_t total;
+    base = block_excl_sum(tsum, sh, &total);
+  }
+  if (gmax > (uint32_t)kBucketMax) {
+    team_sync<TW>();
+    return false;
+  }
+  // counters become exclusive starts (two 16-bit halves per word)
+  if (per >= 2) {
+    for (uint32_t j = 0; j < per; j += 2) {
+      const uint32_t b = b0 + j;
+      if (b < nb) {
+        const uint32_t v0 = c16_get(cnt, b), v1 = c16_get(cnt, b + 1);
+        cnt[b >> 1] = base | ((base + v0) << 16);
+        base += v0 + v1;
+      }
+    }
+  }
+  team_sync<TW>();
+  if (per < 2) {  // (nb < 2*TT) two threads share a word: serialize through a scan of pairs
+    // per == 1: thread tid owns bucket tid; build words from even/odd neighbours
+    const uint32_t b = b0;
+    uint32_t mine = (b < nb) ? base : 0u;
+    const uint32_t other = __shfl_xor(mine, 1);
+    team_sync<TW>();
+    if (b < nb && (b & 1u) == 0u) cnt[b >> 1] = mine | (other << 16);
+    team_sync<TW>();
+  }
+  // place the words
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * TT + tid;
+    if (i < n) {
+      const uint64_t dlt = key[r] - mn;
+      const uint32_t b = (uint32_t)(dlt >> shb);
+      const uint32_t sft = (b & 1u) * 16u;
+      const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sft);
+      const uint32_t pos = min((old >> sft) & 0xFFFFu, (uint32_t)(TT * R) - 1);
+      kb[pos] = (dlt << 12) | i;
+    }
+  }
+  team_sync<TW>();
+  // insertion sort inside each bucket: bucket b spans [end(b-1), end(b))
+  for (uint32_t b = tid; b < nb; b += TT) {
+    const uint32_t e = c16_get(cnt, b);
+    const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
+    for (uint32_t i = s0 + 1; i < e; ++i) {
+      const uint64_t v = kb[i];
+      uint32_t j = i;
+      while (j > s0 && kb[j - 1] > v) {
+        kb[j] = kb[j - 1];
+        --j;
+      }
+      kb[j] = v;
+    }
+  }
+  team_sync<TW>();
+  for (uint32_t i = tid; i < n; i += TT) {
+    const uint64_t v = kb[i];
+    dst[start + i] = (v >> 12) + mn;
+    if constexpr (PW != 0) pay_store<PW>(pdst, start + i, pb[v & 4095u]);
+  }
+  team_sync<TW>();
+  return true;
+}
+
+__device__ void push_hard(Ws& ws, int S, const Leaf& lf) {
+  const uint32_t h = atomicAdd(&ws.ctl->nhard[S], 1u);
+  if (h < ws.leaf_cap) ws.hard[S][h] = lf;
+  else atomicOr(&ws.ctl->error, ERR_LEAFCAP);
+}
+
+template <int PW>
+__global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
+  using Sm = FastSmem<PW>;
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
@@ -1309,6 +1572,7 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   void* pdst = ws.pay[0];
   const uint32_t wv = wave(), ln = lane();
   const int t = threadIdx.x;
+  uint64_t moved = 0;  // keys this thread accounted for (statistics only)
 
   // block jobs: copies of all-identical segments and groups of > kWaveCap keys
   for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
@@ -1316,33 +1580,35 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
     const uint64_t* __restrict__ src = ws.keys[lf.src];
     const void* psrc = ws.pay[lf.src];
     const uint32_t n = lf.count;
-    if (t == 0 && (lf.src != 0 || (!(lf.flags & LF_COPY) && n > 1)))
-      atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)n);
-    if ((lf.flags & LF_COPY) || n <= 1 || n > (uint32_t)kLocalCap) {
+    if (t == 0 && (lf.src != 0 || (!(lf.flags & LF_COPY) && n > 1))) moved += n;
+    if ((lf.flags & LF_COPY) || n <= 1) {
       if (lf.src != 0)
         for (uint32_t i = t; i < n; i += kBlock) {
           dst[lf.start + i] = src[lf.start + i];
           if constexpr (PW != 0) pay_store<PW>(pdst, lf.start + i, pay_load<PW>(psrc, lf.start + i));
         }
-      if (!(lf.flags & LF_COPY) && n > (uint32_t)kLocalCap && t == 0)
-        atomicOr(&c->error, ERR_LEAFCAP);
       continue;
     }
-    team_sort<PW, kWaves>(sm.k, sm.pay, sm.cnt, sm.tot[0], sm.rmin, sm.rmax, sm.sh, src, psrc, dst,
-                          pdst, lf.start, n, (uint32_t)t);
+    if (n > (uint32_t)kBlockCap) {  // not produced by the grouping; left to the fallback
+      if (t == 0) push_hard(ws, S, lf);
+      continue;
+    }
+    const bool ok = fast_sort<PW, kWaves, kBlockCap / kBlock>(
+        sm.k, sm.pay, sm.cnt, sm.rmin, sm.rmax, sm.sh, src, psrc, dst, pdst, lf.start, n,
+        (uint32_t)t);
+    if (!ok && t == 0) push_hard(ws, S, lf);
   }
   __syncthreads();
   // wave jobs: groups of <= kWaveCap keys, one wave each
-  constexpr uint32_t kWaveWords = kWaveCap + kWaveCap / 16;
-  uint64_t* kb = sm.k + wv * kWaveWords;
+  uint64_t* kb = sm.k + wv * kWaveCap;
   typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
+  uint32_t* cb = sm.cnt + wv * (kWaveCap / 2);
   for (uint32_t g = blockIdx.x * kWaves + wv; g < nlw; g += gridDim.x * kWaves) {
     const Leaf lf = ws.leavesw[S][g];
     const uint64_t* __restrict__ src = ws.keys[lf.src];
     const void* psrc = ws.pay[lf.src];
     const uint32_t n = lf.count;
-    if (ln == 0 && (lf.src != 0 || n > 1))
-      atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)n);
+    if (ln == 0 && (lf.src != 0 || n > 1)) moved += n;
     if (n <= 1) {
       if (lf.src != 0 && ln == 0 && n == 1) {
         dst[lf.start] = src[lf.start];
@@ -1350,8 +1616,25 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
       }
       continue;
     }
-    team_sort<PW, 1>(kb, pb, &sm.cnt[wv], sm.tot[wv], nullptr, nullptr, nullptr, src, psrc, dst,
-                     pdst, lf.start, n, ln);
+    bool ok;
+    if (n <= 4 * kWave)
+      ok = fast_sort<PW, 1, 4>(kb, pb, cb, nullptr, nullptr, nullptr, src, psrc, dst, pdst,
+                               lf.start, n, ln);
+    else
+      ok = fast_sort<PW, 1, kWaveCap / kWave>(kb, pb, cb, nullptr, nullptr, nullptr, src, psrc,
+                                              dst, pdst, lf.start, n, ln);
+    if (!ok && ln == 0) push_hard(ws, S, lf);
+  }
+  // one statistics atomic per workgroup
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) moved += __shfl_xor(moved, o);
+  __syncthreads();
+  if (ln == 0) sm.rmin[wv] = moved;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t tot = 0;
+    for (int q = 0; q < kWaves; ++q) tot += sm.rmin[q];
+    if (tot) atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)tot);
   }
 }
 
@@ -1365,7 +1648,8 @@ static const void* stage_fn(int stage) {
     case STAGE_FINALIZE: return (const void*)k_finalize;
     case STAGE_HIST: return (const void*)k_hist<KMAX>;
     case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS>;
-    default: return (const void*)k_local<PW>;
+    case STAGE_LOCAL: return (const void*)k_local<PW>;
+    default: return (const void*)k_local_hard<PW>;
   }
 }
 
@@ -1385,8 +1669,11 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(grid), dim3(kBlock), 0, st, ws,
                          L);
       break;
-    default:
+    case STAGE_LOCAL:
       hipLaunchKernelGGL((k_local<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      break;
+    default:
+      hipLaunchKernelGGL((k_local_hard<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
   }
 }
@@ -1414,36 +1701,44 @@ hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, 
   return hipGetLastError();
 }
 
-#define ZS_DISPATCH(KM, KB, CALL)                     \
-  if (k <= KM) {                                      \
-    if (pw == 0) CALL(KM, KB, 0);                      \
-    else if (pw == 4) CALL(KM, KB, 4);                 \
-    else CALL(KM, KB, 8);                              \
-  }
+// (k, payload bytes, tile) -> template instance; KMAX 4096 only with 2048-key tiles
+#define ZS_DISPATCH(CALL)                                                   \
+  do {                                                                      \
+    const int r16 = ws_tile == 4096;                                        \
+    if (k <= 256) {                                                         \
+      if (pw == 0) { if (r16) CALL(256, 8, 0, 16); else CALL(256, 8, 0, 8); } \
+      else if (pw == 4) { if (r16) CALL(256, 8, 4, 16); else CALL(256, 8, 4, 8); } \
+      else { if (r16) CALL(256, 8, 8, 16); else CALL(256, 8, 8, 8); }       \
+    } else if (k <= 512) {                                                  \
+      if (pw == 0) { if (r16) CALL(512, 9, 0, 16); else CALL(512, 9, 0, 8); } \
+      else if (pw == 4) { if (r16) CALL(512, 9, 4, 16); else CALL(512, 9, 4, 8); } \
+      else { if (r16) CALL(512, 9, 8, 16); else CALL(512, 9, 8, 8); }       \
+    } else if (k <= 1024) {                                                 \
+      if (pw == 0) { if (r16) CALL(1024, 10, 0, 16); else CALL(1024, 10, 0, 8); } \
+      else if (pw == 4) { if (r16) CALL(1024, 10, 4, 16); else CALL(1024, 10, 4, 8); } \
+      else { if (r16) CALL(1024, 10, 8, 16); else CALL(1024, 10, 8, 8); }   \
+    } else {                                                                \
+      if (pw == 0) CALL(4096, 12, 0, 8);                                    \
+      else if (pw == 4) CALL(4096, 12, 4, 8);                               \
+      else CALL(4096, 12, 8, 8);                                            \
+    }                                                                       \
+  } while (0)
 
 hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st) {
   const int k = ws.p.k;
   const int pw = ws.p.pw;
-#define ZS_LAUNCH(KM, KB, PWV)                                   \
-  do {                                                           \
-    launch_stage_t<KM, KB, PWV, 8>(ws, L, stage, grid, st);      \
-    return hipGetLastError();                                    \
-  } while (0)
-  ZS_DISPATCH(1024, 10, ZS_LAUNCH)
-  ZS_DISPATCH(4096, 12, ZS_LAUNCH)
+  const int ws_tile = ws.p.tile;
+#define ZS_LAUNCH(KM, KB, PWV, R) launch_stage_t<KM, KB, PWV, R>(ws, L, stage, grid, st)
+  ZS_DISPATCH(ZS_LAUNCH);
 #undef ZS_LAUNCH
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // resident workgroups per compute unit of a stage's kernel (at least 1)
-int stage_blocks_per_cu(int k, int pw, int stage) {
+int stage_blocks_per_cu(int k, int pw, int ws_tile, int stage) {
   const void* fn = nullptr;
-#define ZS_FN(KM, KB, PWV)                                       \
-  do {                                                           \
-    fn = stage_fn<KM, KB, PWV, 8>(stage);                        \
-  } while (0)
-  ZS_DISPATCH(1024, 10, ZS_FN)
-  else ZS_DISPATCH(4096, 12, ZS_FN)
+#define ZS_FN(KM, KB, PWV, R) fn = stage_fn<KM, KB, PWV, R>(stage)
+  ZS_DISPATCH(ZS_FN);
 #undef ZS_FN
   if (!fn) return 1;
   int nb = 0;

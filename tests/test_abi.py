@@ -38,8 +38,9 @@ def test_host_only_entry_points():
     assert (c.k, c.cutoff, c.max_zlevels, c.chunk) == (1024, 2048, 8, 16384)
     assert zs.strerror(0) == "ok" and zs.strerror(-1) == "invalid argument"
     b = zs.zsort_workspace_bytes(10**8, 4, 0)
-    # alternate buffer (12 B/key) dominates; look-back and starts are small
-    assert 12 * 10**8 <= b <= 16 * 10**8
+    # the alternate buffer (12 B/key) dominates; lists, look-back words and
+    # cluster starts add a few bytes per key
+    assert 12 * 10**8 <= b <= 20 * 10**8
     assert zs.zsort_workspace_bytes(10**8, 3, 0) == 0        # bad payload width
     assert zs.zsort_workspace_bytes(100, 4, 0, dict(k=8)) == 0  # k below 16
     assert zs.zsort_workspace_bytes(100, 4, 0, dict(cutoff=4096)) == 0
