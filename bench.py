@@ -101,6 +101,9 @@ def run_workload(spec, steps, warmup, cfg, dev, profile=True):
     log(f"[bench] {spec['workload']} n={spec['n']} generated in {time.time() - t0:.1f}s")
     base_k, base_p = to_device(keys, pay, dev)
     del pay
+    if cfg is None:  # the library's autotuner picks k / tile / chunk / cutoff
+        cfg = zs.zsort_autotune(base_k, base_p)
+        log(f"[bench] tuned {cfg}")
     ins = [(base_k.clone(), None if base_p is None else base_p.clone()) for _ in range(steps)]
     for _ in range(warmup):
         k = base_k.clone()
@@ -125,7 +128,71 @@ def run_workload(spec, steps, warmup, cfg, dev, profile=True):
     log(f"[bench] {spec['workload']}: {ms:.3f} ms/step, levels {stats['levels']}, verified")
     del ins
     torch.cuda.empty_cache()
-    return keys, ms, stats, kt
+    return keys, ms, stats, kt, cfg
+
+
+def run_batched(steps, warmup, dev, nseg=4096):
+    """Batched form: nseg arrays in one segmented call replayed as a cached
+    hipGraph, against a loop of plain single-array calls (one per segment)."""
+    import synth
+    import torch
+    import paper_2605_14419_amd as zs
+
+    keys, off, idx = synth.segments(nseg, synth.seed_for(3, 0))
+    n = keys.size
+    log(f"[bench] batched: {nseg} arrays, {n} keys")
+    base_k, base_p = to_device(keys, idx, dev)
+    toff = torch.from_numpy(off).to(dev)
+    cfg = zs.zsort_autotune(base_k, base_p, toff)
+    gcfg = dict(cfg, flags=zs.ZSORT_FLAG_GRAPH)
+    bufs = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
+    for k, p in bufs:  # capture one graph per buffer pair (not timed)
+        zs.zsort_stable_segmented(k, toff, p, gcfg)
+    for _ in range(warmup):
+        zs.zsort_stable_segmented(bufs[0][0], toff, bufs[0][1], gcfg)
+    for k, p in bufs:
+        k.copy_(base_k)
+        p.copy_(base_p)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for k, p in bufs:
+        zs.zsort_stable_segmented(k, toff, p, gcfg)
+    ev1.record()
+    torch.cuda.synchronize()
+    g_ms = ev0.elapsed_time(ev1) / steps
+    st = zs.zsort_get_last_stats()
+    assert st["device_error"] == 0, st
+    gk = bufs[-1][0].cpu().numpy().view(np.uint64)
+    # the loop of plain calls on views of each segment (same tuned config, paced)
+    lk, lp = base_k.clone(), base_p.clone()
+    offs = off.tolist()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ev0.record()
+    for i in range(nseg):
+        a, b = offs[i], offs[i + 1]
+        if b - a > 1:
+            zs.zsort_stable_ex(lk[a:b], lp[a:b], cfg)
+    ev1.record()
+    torch.cuda.synchronize()
+    l_ms = ev0.elapsed_time(ev1)
+    log(f"[bench] batched graph {g_ms:.3f} ms/step, loop {l_ms:.1f} ms "
+        f"(host {1e3 * (time.time() - t0):.1f} ms)")
+    assert np.array_equal(lk.cpu().numpy().view(np.uint64), gk), "loop and graph disagree"
+    for i in range(0, nseg, max(1, nseg // 16)):  # spot-check segments
+        a, b = offs[i], offs[i + 1]
+        seg = gk[a:b]
+        assert np.all(seg[1:] >= seg[:-1])
+    del bufs
+    torch.cuda.empty_cache()
+    return {"workload": f"{nseg} arrays, lognormal lengths (median 2e4, [100, 1e6]), "
+                        f"{n} u64 keys from per-array normals, u32 index payload",
+            "n": n, "config": cfg,
+            "graph_ms_per_step": round(g_ms, 4), "graph_gkeys_per_s": round(n / g_ms / 1e6, 3),
+            "loop_ms_per_step": round(l_ms, 3), "loop_gkeys_per_s": round(n / l_ms / 1e6, 4),
+            "speedup_vs_loop": round(l_ms / g_ms, 2)}
 
 
 def roofline(kt, stats, pw, steps, traffic_file):
@@ -170,7 +237,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--extras", default=",".join(EXTRAS), help="comma list, or 'none'")
+    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["batched"]),
+                    help="comma list, or 'none'")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=PRIMARY["n"])
@@ -188,7 +256,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     zs.lib()  # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
-    cfg = dict(DEFAULT_CFG)
     spec = dict(PRIMARY, n=args.n)
 
     if args.copy_probe:
@@ -199,7 +266,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies")
-    keys, ms, stats, kt = run_workload(spec, args.steps, args.warmup, cfg, dev)
+    keys, ms, stats, kt, cfg = run_workload(spec, args.steps, args.warmup, None, dev)
     pw = spec["payload_bytes"]
     n = spec["n"]
     value = n / (ms * 1e-3) / 1e9
@@ -222,8 +289,11 @@ def main():
     extras = {}
     if args.extras and args.extras != "none":
         for name in args.extras.split(","):
+            if name == "batched":
+                extras[name] = run_batched(max(3, args.steps // 2), 1, dev)
+                continue
             es = EXTRAS[name]
-            ek, ems, est, ekt = run_workload(es, max(3, args.steps // 2), 1, cfg, dev)
+            ek, ems, est, ekt, ecfg = run_workload(es, max(3, args.steps // 2), 1, None, dev)
             del ek
             epw = es["payload_bytes"]
             extras[name] = {
@@ -232,7 +302,7 @@ def main():
                 "hbm_frac_effective": round(est["model_bytes"] / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "hbm_frac_sort_equivalent": round(2 * (8 + epw) * es["n"] / (ems * 1e-3) / 1e9
                                                   / HBM_PEAK_GBS, 4),
-                "levels": est["levels"],
+                "levels": est["levels"], "config": ecfg,
                 "kernel_ms_per_step": {s: round(ekt[s][0] / max(3, args.steps // 2), 4)
                                        for s in STAGES},
             }

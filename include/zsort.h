@@ -64,18 +64,44 @@ enum {
  *                [2048, 2^20] (and of tile).  Default 16384.
  *   tile         keys a workgroup stages through LDS per step of the stable
  *                scatter: 2048 or 4096 (4096 needs k <= 1024).  Default 2048.
+ *   flags        ZSORT_FLAG_GRAPH: run the whole sort as one cached hipGraph
+ *                (every level of the recursion is launched; kernels of empty
+ *                levels exit at once).  The graph is captured on a private
+ *                stream at the first call with a given set of buffers, shape
+ *                and configuration, and replayed on `stream` afterwards.
+ *                Without the flag the library launches level by level and
+ *                stops one level after the recursion ends, waiting on the
+ *                device's progress between levels (host-side pacing).
  */
+#define ZSORT_FLAG_GRAPH 1
 typedef struct zsort_config {
   int32_t k;
   int32_t cutoff;
   int32_t max_zlevels;
   int32_t chunk;
   int32_t tile;
-  int32_t reserved[3];
+  int32_t flags;
+  int32_t reserved[2];
 } zsort_config;
 
 /* Fills cfg with the defaults above.  Returns ZSORT_OK or ZSORT_EINVAL (null). */
 int zsort_default_config(zsort_config* cfg);
+
+/*
+ * Autotuner: times candidate configurations (k in {256, 512, 1024}, tile in
+ * {2048, 4096} with chunk 16384 / 32768, cutoff in {1024, 2048}) on a scratch
+ * copy of keys/payload (device buffers, left unchanged; seg_offsets may be
+ * NULL for a single array) and remembers the fastest for the shape class
+ * (n rounded up to a power of two, payload width, single or segmented).
+ * Later calls of that class with cfg == NULL use it.  If the class is already
+ * known no timing is done.  cache_path (may be NULL) names a text file of
+ * tuned entries that is read first and rewritten afterwards.  best (host, may
+ * be NULL) receives the chosen configuration.  Synchronous; allocates scratch
+ * memory for the copies.
+ */
+int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes, size_t n,
+                   const int64_t* seg_offsets, int32_t num_segments, const char* cache_path,
+                   zsort_config* best, void* stream);
 
 /*
  * Stable sort of keys[0, n) with an optional u32 payload (payload may be

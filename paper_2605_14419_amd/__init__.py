@@ -23,15 +23,17 @@ EXPORTED = [
     "zsort_default_config", "zsort_stable", "zsort_stable_p64", "zsort_stable_ex",
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
-    "zsort_strerror", "zsort_profile_begin", "zsort_profile_end",
+    "zsort_strerror", "zsort_profile_begin", "zsort_profile_end", "zsort_autotune",
 ]
+ZSORT_FLAG_GRAPH = 1
 STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
 
 
 class ZsortConfig(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("max_zlevels", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tile", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class ZsortStats(ctypes.Structure):
@@ -87,6 +89,7 @@ def lib():
         L.zsort_debug_level0.argtypes = [P, P, I, Z, P, P, P, P]
         L.zsort_stable_traced.argtypes = [P, P, I, Z, P, P, ctypes.c_int64, P, ctypes.c_int64,
                                           P, P]
+        L.zsort_autotune.argtypes = [P, P, I, Z, P, ctypes.c_int32, ctypes.c_char_p, P, P]
         L.zsort_profile_begin.argtypes = [P]
         L.zsort_profile_end.argtypes = [P, P]
         L.zsort_strerror.argtypes = [I]
@@ -226,6 +229,19 @@ def zsort_stable_traced(keys, payload=None, cfg=None, trace_cap=1 << 16, hist_ca
                                    counts.ctypes.data, _stream(stream))
     _check("zsort_stable_traced", rc)
     return rec[: min(int(counts[0]), trace_cap)], hist[: int(counts[1])]
+
+
+def zsort_autotune(keys, payload=None, seg_offsets=None, cache_path=None, stream=None) -> dict:
+    """Tunes k / tile / chunk / cutoff for arrays shaped like `keys` (left
+    unchanged) and returns the chosen configuration as a dict."""
+    p, pw = _pay(payload, keys.numel())
+    best = ZsortConfig()
+    off = None if seg_offsets is None else ctypes.c_void_p(seg_offsets.data_ptr())
+    nseg = 0 if seg_offsets is None else seg_offsets.numel() - 1
+    _check("zsort_autotune", lib().zsort_autotune(
+        _keys_ptr(keys), p, pw, keys.numel(), off, nseg,
+        None if cache_path is None else cache_path.encode(), ctypes.byref(best), _stream(stream)))
+    return {f: getattr(best, f) for f in ("k", "cutoff", "max_zlevels", "chunk", "tile")}
 
 
 def zsort_profile_begin(stream=None):

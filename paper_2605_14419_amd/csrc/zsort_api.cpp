@@ -5,8 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -88,6 +91,21 @@ Layout plan(const Shape& s) {
   return L;
 }
 
+// cached hipGraph of one whole sort: the kernels' arguments (caller's buffers,
+// workspace layout, configuration) are baked into the graph
+struct GraphKey {
+  const void* keys;
+  const void* pay;
+  const void* off;
+  uint64_t n;
+  int32_t nseg;
+  int pw, k, cutoff, maxz, chunk, tile;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(keys, pay, off, n, nseg, pw, k, cutoff, maxz, chunk, tile) <
+           std::tie(o.keys, o.pay, o.off, o.n, o.nseg, o.pw, o.k, o.cutoff, o.maxz, o.chunk, o.tile);
+  }
+};
+
 struct Workspace {
   int device = -1;
   char* base = nullptr;
@@ -110,7 +128,15 @@ struct Workspace {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_stage;  // stage of each (start, end) pair
+  // graph mode
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
 };
+
+void drop_graphs(Workspace* w) {
+  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+  w->graphs.clear();
+}
 
 hipError_t next_event(Workspace* w, hipEvent_t* ev) {
   if (w->ev_used == w->ev_pool.size()) {
@@ -191,6 +217,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out) {
   const bool same = w->laid_out && w->shape == s;
   if (!same) {
     if (capturing(st)) return ZSORT_ECAPTURE;
+    drop_graphs(w);
     if (L.total > w->bytes) {
       if (w->base) {
         e = hipFree(w->base);
@@ -308,6 +335,8 @@ bool pacing_ready(Workspace* w) {
   return true;
 }
 
+hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st);
+
 int run(const Call& c, hipStream_t st, Workspace** wout) {
   Shape s;
   s.n = c.n;
@@ -323,6 +352,52 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   int rc = acquire(st, s, &w);
   if (rc) return rc;
   const Ws ws = make_ws(w, c.keys, c.pay, c.cfg, c.pw);
+  hipError_t e = hipSuccess;
+  const bool graph = (c.cfg.flags & ZSORT_FLAG_GRAPH) && !c.level0_only && !c.trace_cap &&
+                     !capturing(st);
+  if (graph) {
+    GraphKey gk{c.keys, c.pay, c.off, c.n, c.off ? c.nseg : 0, c.pw, c.cfg.k, c.cfg.cutoff,
+                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile};
+    auto it = w->graphs.find(gk);
+    hipGraphExec_t ex = nullptr;
+    if (it != w->graphs.end()) {
+      ex = it->second;
+    } else {
+      if (!w->cap_stream) {
+        e = hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      const bool prof = w->prof;
+      w->prof = false;
+      e = hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = enqueue(w, ws, c, w->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(w->cap_stream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+      }
+      w->prof = prof;
+      if (e != hipSuccess) return hip_fail(e);
+      w->graphs[gk] = ex;
+    }
+    e = hipGraphLaunch(ex, st);
+    if (e != hipSuccess) return hip_fail(e);
+  } else {
+    e = enqueue(w, ws, c, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  w->calls++;
+  w->last_n = c.n;
+  w->last_pw = c.pw;
+  w->has_last = true;
+  if (wout) *wout = w;
+  return ZSORT_OK;
+}
+
+// the launch sequence of one sort on stream st
+hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
   hipError_t e = zs::launch_reset(ws, st);
   if (e == hipSuccess) {
     if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
@@ -351,18 +426,61 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
       if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[L], st);
     }
   }
-  if (e != hipSuccess) return hip_fail(e);
-  w->calls++;
-  w->last_n = c.n;
-  w->last_pw = c.pw;
-  w->has_last = true;
-  if (wout) *wout = w;
-  return ZSORT_OK;
+  return e;
 }
 
-int resolve_cfg(const zsort_config* in, zsort_config* out) {
+// ---- tuned configurations, by shape class -------------------------------
+struct TuneKey {
+  int ncls, pw, seg;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(ncls, pw, seg) < std::tie(o.ncls, o.pw, o.seg);
+  }
+};
+std::map<TuneKey, zsort_config> g_tuned;
+
+int n_class(uint64_t n) {
+  int c = 0;
+  while (c < 63 && (1ull << c) < n) ++c;
+  return c;
+}
+
+void tune_file_read(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    TuneKey tk;
+    zsort_config c;
+    zsort_default_config(&c);
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &tk.ncls, &tk.pw, &tk.seg, &c.k, &c.cutoff,
+                    &c.max_zlevels, &c.chunk, &c.tile) == 8 &&
+        check_cfg(&c) == ZSORT_OK)
+      g_tuned[tk] = c;
+  }
+  std::fclose(f);
+}
+
+void tune_file_write(const char* path) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "# n_class payload_bytes segmented k cutoff max_zlevels chunk tile\n");
+  for (auto& kv : g_tuned)
+    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", kv.first.ncls, kv.first.pw, kv.first.seg,
+                 kv.second.k, kv.second.cutoff, kv.second.max_zlevels, kv.second.chunk,
+                 kv.second.tile);
+  std::fclose(f);
+}
+
+// cfg given: validated as is; cfg NULL: the tuned entry of the class, else defaults
+int resolve_cfg(const zsort_config* in, zsort_config* out, uint64_t n = 0, int pw = 0,
+                int seg = 0) {
   zsort_default_config(out);
-  if (in) *out = *in;
+  if (in) {
+    *out = *in;
+  } else if (n) {
+    auto it = g_tuned.find(TuneKey{n_class(n), pw, seg});
+    if (it != g_tuned.end()) *out = it->second;
+  }
   return check_cfg(out);
 }
 
@@ -386,6 +504,7 @@ int zsort_default_config(zsort_config* cfg) {
   cfg->max_zlevels = 8;
   cfg->chunk = 16384;
   cfg->tile = 2048;
+  cfg->flags = 0;
   return ZSORT_OK;
 }
 
@@ -393,11 +512,11 @@ int zsort_stable_ex(uint64_t* keys, void* payload, int payload_bytes, size_t n,
                     const zsort_config* cfg, void* stream) {
   int rc = common_checks(keys, payload, payload_bytes, n);
   if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
   zsort_config c;
-  rc = resolve_cfg(cfg, &c);
+  rc = resolve_cfg(cfg, &c, n, payload_bytes, 0);
   if (rc) return rc;
   if (n <= 1) return ZSORT_OK;
-  std::lock_guard<std::mutex> lk(g_mu);
   Call call{keys, payload_bytes ? payload : nullptr, payload_bytes, (uint64_t)n, nullptr, 0, c,
             0, 0, false};
   return run(call, (hipStream_t)stream, nullptr);
@@ -417,11 +536,11 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
   int rc = common_checks(keys, payload, payload_bytes, n);
   if (rc) return rc;
   if (num_segments < 0 || (num_segments > 0 && !seg_offsets)) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
   zsort_config c;
-  rc = resolve_cfg(cfg, &c);
+  rc = resolve_cfg(cfg, &c, n, payload_bytes, 1);
   if (rc) return rc;
   if (n <= 1 || num_segments == 0) return ZSORT_OK;
-  std::lock_guard<std::mutex> lk(g_mu);
   Call call{keys, payload_bytes ? payload : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
             num_segments, c, 0, 0, false};
   return run(call, (hipStream_t)stream, nullptr);
@@ -543,6 +662,80 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
     if (e != hipSuccess) return hip_fail(e);
   }
   return ctl.error ? ZSORT_EDEVICE : ZSORT_OK;
+}
+
+int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes, size_t n,
+                   const int64_t* seg_offsets, int32_t num_segments, const char* cache_path,
+                   zsort_config* best, void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  if (num_segments < 0 || (num_segments > 0 && !seg_offsets)) return ZSORT_EINVAL;
+  const int seg = seg_offsets ? 1 : 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (cache_path) tune_file_read(cache_path);
+  const TuneKey key{n_class(n), payload_bytes, seg};
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end() || n <= 1) {
+    if (best) resolve_cfg(nullptr, best, n, payload_bytes, seg);
+    return ZSORT_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (capturing(st)) return ZSORT_ECAPTURE;
+  uint64_t* tk = nullptr;
+  void* tp = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&tk, n * 8);
+  if (e == hipSuccess && payload_bytes) e = hipMalloc(&tp, n * (size_t)payload_bytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  zsort_config win;
+  zsort_default_config(&win);
+  float win_ms = 1e30f;
+  const int ks[3] = {256, 512, 1024};
+  const int tiles[2] = {2048, 4096};
+  const int cuts[2] = {1024, 2048};
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+        zsort_config c;
+        zsort_default_config(&c);
+        c.k = ks[a];
+        c.tile = tiles[b];
+        c.chunk = tiles[b] == 4096 ? 32768 : 16384;
+        c.cutoff = cuts[d];
+        float t_best = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipMemcpyAsync(tk, keys, n * 8, hipMemcpyDeviceToDevice, st);
+          if (e == hipSuccess && payload_bytes)
+            e = hipMemcpyAsync(tp, payload, n * (size_t)payload_bytes, hipMemcpyDeviceToDevice, st);
+          if (e == hipSuccess) e = hipEventRecord(e0, st);
+          if (e != hipSuccess) break;
+          Call call{tk, payload_bytes ? tp : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
+                    num_segments, c, 0, 0, false};
+          rc = run(call, st, nullptr);
+          if (rc) break;
+          e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && ms < t_best) t_best = ms;  // first run warms up
+        }
+        if (rc) break;
+        if (t_best < win_ms) {
+          win_ms = t_best;
+          win = c;
+        }
+      }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (tk) (void)hipFree(tk);
+  if (tp) (void)hipFree(tp);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e);
+  g_tuned[key] = win;
+  if (cache_path) tune_file_write(cache_path);
+  if (best) *best = win;
+  return ZSORT_OK;
 }
 
 int zsort_profile_begin(void* stream) {
