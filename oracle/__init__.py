@@ -59,6 +59,17 @@ def lib():
         L.zo_brute_stable_sort.argtypes = [P, P, I32, U64]
         L.zo_brute_stable_sort.restype = I32
         L.zo_seg_rec_size.restype = I32
+        L.zo_mlp_norm.argtypes = [U64, U64, U64]
+        L.zo_mlp_norm.restype = D
+        L.zo_mlp_forward.argtypes = [P, D]
+        L.zo_mlp_forward.restype = ctypes.c_float
+        L.zo_mlp_bucket.argtypes = [P, U64, U64, U64, I32]
+        L.zo_mlp_bucket.restype = I32
+        L.zo_mlp_thresholds.argtypes = [P, U64, U64, I32, P]
+        L.zo_mlp_thresholds.restype = I32
+        L.zo_mlp_init.argtypes = [P, U64, U64, U64, P]
+        L.zo_mlp_loss_grad.argtypes = [P, P, P, U64, P]
+        L.zo_mlp_loss_grad.restype = D
         assert L.zo_seg_rec_size() == SEG_REC.itemsize
         _lib = L
     return _lib
@@ -205,3 +216,69 @@ def brute_stable_sort(keys, payload=None):
     if rc:
         raise ValueError("bad arguments")
     return x, p
+
+
+# ---------------------------------------------------------------------------
+# learned partition: monotone MLP CDF (1 -> 32 -> 32 -> 1), 1153 parameters
+# ---------------------------------------------------------------------------
+MLP_NP = 1153
+MLP_H = 32
+W1, B1, W2, B2, W3, B3 = 0, 32, 64, 1088, 1120, 1152
+
+
+def _f32(p):
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    assert p.size == MLP_NP
+    return p
+
+
+def mlp_norm(x: int, smin: int, smax: int) -> float:
+    return lib().zo_mlp_norm(x, smin, smax)
+
+
+def mlp_forward(p, u: float) -> float:
+    p = _f32(p)
+    return float(lib().zo_mlp_forward(p.ctypes.data, u))
+
+
+def mlp_bucket(p, x: int, smin: int, smax: int, B: int) -> int:
+    p = _f32(p)
+    return int(lib().zo_mlp_bucket(p.ctypes.data, x, smin, smax, B))
+
+
+def mlp_buckets(p, xs, smin, smax, B):
+    p = _f32(p)
+    f = lib().zo_mlp_bucket
+    return np.array([f(p.ctypes.data, int(x), smin, smax, B) for x in xs], dtype=np.int64)
+
+
+def mlp_thresholds(p, smin: int, smax: int, B: int):
+    p = _f32(p)
+    out = np.zeros(B - 1, dtype=np.uint64)
+    nt = lib().zo_mlp_thresholds(p.ctypes.data, smin, smax, B, out.ctypes.data)
+    return int(nt), out
+
+
+def mlp_init(sorted_sample, smin: int, smax: int):
+    s = np.ascontiguousarray(sorted_sample, dtype=np.uint64)
+    p = np.zeros(MLP_NP, dtype=np.float32)
+    lib().zo_mlp_init(s.ctypes.data, s.size, smin, smax, p.ctypes.data)
+    return p
+
+
+def mlp_loss_grad(p, u, y):
+    p = _f32(p)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.zeros(MLP_NP, dtype=np.float64)
+    loss = lib().zo_mlp_loss_grad(p.ctypes.data, u.ctypes.data, y.ctypes.data, u.size,
+                                  g.ctypes.data)
+    return float(loss), g
+
+
+def mlp_targets(sorted_sample):
+    """mid-rank empirical CDF of a sorted sample: (rank_lt + rank_le) / (2m)"""
+    s = np.asarray(sorted_sample, dtype=np.uint64)
+    lo = np.searchsorted(s, s, side="left")
+    hi = np.searchsorted(s, s, side="right")
+    return (lo + hi) / (2.0 * s.size)

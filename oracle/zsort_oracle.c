@@ -583,3 +583,150 @@ int zo_brute_stable_sort(uint64_t *keys, void *payload, int pw, uint64_t n)
 }
 
 int zo_seg_rec_size(void) { return (int)sizeof(zo_seg_rec); }
+
+/* ====================================================================== */
+/* Learned partition (an extension beyond the paper): a monotone MLP that  */
+/* approximates the keys' CDF and replaces the z-score map at the first    */
+/* pass.  Parameter layout (1153 floats): W1[32] b1[32] W2[32][32] (row =  */
+/* output unit) b2[32] W3[32] b3.  Non-negative weights and clamp ramps    */
+/* make f non-decreasing.                                                  */
+/* ====================================================================== */
+enum { ZO_H = 32, ZO_NP = 1153, ZO_W1 = 0, ZO_B1 = 32, ZO_W2 = 64, ZO_B2 = 1088, ZO_W3 = 1120,
+       ZO_B3 = 1152 };
+
+static float clamp01f(float a) { return a < 0.0f ? 0.0f : (a > 1.0f ? 1.0f : a); }
+
+/* normalised key: 0 at or below smin, 1 at or above smax, else the ratio */
+double zo_mlp_norm(uint64_t x, uint64_t smin, uint64_t smax)
+{
+    if (x <= smin) return 0.0;
+    if (x >= smax) return 1.0;
+    return (double)(x - smin) / (double)(smax - smin);
+}
+
+/* Inference in the precision both sides use: the first layer's
+ * pre-activation in binary64, rounded to binary32; everything after in
+ * binary32, products and sums rounded separately, sums in index order. */
+float zo_mlp_forward(const float *p, double u)
+{
+    float h1[ZO_H], h2[ZO_H];
+    for (int i = 0; i < ZO_H; i++) {
+        double a = (double)p[ZO_W1 + i] * u;
+        a = a + (double)p[ZO_B1 + i];
+        h1[i] = clamp01f((float)a);
+    }
+    for (int j = 0; j < ZO_H; j++) {
+        float acc = p[ZO_B2 + j];
+        for (int i = 0; i < ZO_H; i++) {
+            float t = p[ZO_W2 + j * ZO_H + i] * h1[i];
+            acc = acc + t;
+        }
+        h2[j] = clamp01f(acc);
+    }
+    float f = p[ZO_B3];
+    for (int j = 0; j < ZO_H; j++) {
+        float t = p[ZO_W3 + j] * h2[j];
+        f = f + t;
+    }
+    return f;
+}
+
+/* cluster of a key under the learned map with B clusters */
+int zo_mlp_bucket(const float *p, uint64_t x, uint64_t smin, uint64_t smax, int B)
+{
+    float f = clamp01f(zo_mlp_forward(p, zo_mlp_norm(x, smin, smax)));
+    float t = (float)B * f;
+    float fl = floorf(t);
+    if (fl >= (float)(B - 1)) return B - 1;
+    return (int)fl;
+}
+
+/* Thresholds t_b = min{x : bucket(x) >= b} for b = 1..nt, where
+ * nt = bucket(2^64 - 1); found by bisection over the u64 keys, which is
+ * exact when the map is non-decreasing.  Returns nt; out gets B-1 words
+ * (unused ones are 0). */
+int zo_mlp_thresholds(const float *p, uint64_t smin, uint64_t smax, int B, uint64_t *out)
+{
+    int nt = zo_mlp_bucket(p, UINT64_MAX, smin, smax, B);
+    for (int b = 1; b < B; b++) out[b - 1] = 0;
+    for (int b = 1; b <= nt; b++) {
+        uint64_t lo = 0, hi = UINT64_MAX;   /* bucket(hi) >= b */
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (zo_mlp_bucket(p, mid, smin, smax, B) >= b) hi = mid;
+            else lo = mid + 1;
+        }
+        out[b - 1] = lo;
+    }
+    return nt;
+}
+
+/* Quantile initialisation from the sorted sample s[0, m): unit i ramps from
+ * 0 to 1 between the sample's i/32 and (i+1)/32 quantiles; the second layer
+ * passes the ramps through; the output averages them.  The result is the
+ * piecewise-linear interpolation of the sample's CDF at 33 knots. */
+void zo_mlp_init(const uint64_t *s, uint64_t m, uint64_t smin, uint64_t smax, float *p)
+{
+    for (int i = 0; i < ZO_NP; i++) p[i] = 0.0f;
+    double q[ZO_H + 1];
+    for (int i = 0; i <= ZO_H; i++) {
+        uint64_t idx = (uint64_t)(((double)i * (double)(m - 1)) / (double)ZO_H);
+        q[i] = zo_mlp_norm(s[idx], smin, smax);
+    }
+    for (int i = 0; i < ZO_H; i++) {
+        double w = q[i + 1] > q[i] ? 1.0 / (q[i + 1] - q[i]) : 1.0e6;
+        p[ZO_W1 + i] = (float)w;
+        p[ZO_B1 + i] = (float)(-q[i] * w);
+        p[ZO_W2 + i * ZO_H + i] = 1.0f;
+        p[ZO_W3 + i] = 1.0f / (float)ZO_H;
+    }
+}
+
+/* Mean squared error over (u[s], y[s]) and its exact gradient in binary64
+ * (the clamp's derivative is 1 strictly inside (0, 1), else 0). */
+double zo_mlp_loss_grad(const float *p, const double *u, const double *y, uint64_t m, double *g)
+{
+    double W1[ZO_H], b1[ZO_H], W2[ZO_H][ZO_H], b2[ZO_H], W3[ZO_H], b3 = p[ZO_B3];
+    for (int i = 0; i < ZO_H; i++) {
+        W1[i] = p[ZO_W1 + i]; b1[i] = p[ZO_B1 + i]; b2[i] = p[ZO_B2 + i]; W3[i] = p[ZO_W3 + i];
+        for (int k = 0; k < ZO_H; k++) W2[i][k] = p[ZO_W2 + i * ZO_H + k];
+    }
+    if (g) for (int i = 0; i < ZO_NP; i++) g[i] = 0.0;
+    double loss = 0.0;
+    for (uint64_t s = 0; s < m; s++) {
+        double a1[ZO_H], h1[ZO_H], a2[ZO_H], h2[ZO_H];
+        for (int i = 0; i < ZO_H; i++) {
+            a1[i] = W1[i] * u[s] + b1[i];
+            h1[i] = a1[i] < 0 ? 0 : (a1[i] > 1 ? 1 : a1[i]);
+        }
+        for (int j = 0; j < ZO_H; j++) {
+            a2[j] = b2[j];
+            for (int i = 0; i < ZO_H; i++) a2[j] += W2[j][i] * h1[i];
+            h2[j] = a2[j] < 0 ? 0 : (a2[j] > 1 ? 1 : a2[j]);
+        }
+        double f = b3;
+        for (int j = 0; j < ZO_H; j++) f += W3[j] * h2[j];
+        double r = f - y[s];
+        loss += r * r / (double)m;
+        if (!g) continue;
+        double e = 2.0 * r / (double)m;
+        double d2[ZO_H], d1[ZO_H];
+        g[ZO_B3] += e;
+        for (int j = 0; j < ZO_H; j++) {
+            g[ZO_W3 + j] += e * h2[j];
+            d2[j] = (a2[j] > 0 && a2[j] < 1) ? e * W3[j] : 0.0;
+            g[ZO_B2 + j] += d2[j];
+        }
+        for (int i = 0; i < ZO_H; i++) {
+            double acc = 0.0;
+            for (int j = 0; j < ZO_H; j++) {
+                g[ZO_W2 + j * ZO_H + i] += d2[j] * h1[i];
+                acc += d2[j] * W2[j][i];
+            }
+            d1[i] = (a1[i] > 0 && a1[i] < 1) ? acc : 0.0;
+            g[ZO_B1 + i] += d1[i];
+            g[ZO_W1 + i] += d1[i] * u[s];
+        }
+    }
+    return loss;
+}

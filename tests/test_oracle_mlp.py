@@ -1,0 +1,132 @@
+"""Pins of the oracle's monotone MLP (learned-partition extension): analytic
+gradient against central finite differences, closed forms of the quantile
+initialisation and of tiny networks, monotonicity, and the defining property
+of the bucket thresholds."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+U64 = 2**64 - 1
+
+
+def random_params(seed, scale=0.5):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(oracle.MLP_NP, dtype=np.float32)
+    p[oracle.W1:oracle.W1 + 32] = rng.uniform(0.5, 3.0, 32)
+    p[oracle.B1:oracle.B1 + 32] = rng.uniform(-1.5, 0.5, 32)
+    p[oracle.W2:oracle.W2 + 1024] = rng.uniform(0.0, scale / 8, 1024)
+    p[oracle.B2:oracle.B2 + 32] = rng.uniform(-0.2, 0.4, 32)
+    p[oracle.W3:oracle.W3 + 32] = rng.uniform(0.0, 0.06, 32)
+    p[oracle.B3] = 0.01
+    return p
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(3)
+    p = random_params(1)
+    u = rng.uniform(0, 1, 200)
+    y = np.sort(rng.uniform(0, 1, 200))
+    loss, g = oracle.mlp_loss_grad(p, u, y)
+    # the loss is evaluated in float64 from float32 parameters: perturb by a
+    # small exact float32 step (so that no clamp kink is crossed) and divide
+    # by the step actually taken
+    checked = 0
+    for idx in list(range(0, 64, 7)) + list(range(64, 1088, 97)) + list(range(1088, 1153, 5)):
+        h = np.float32(2.0**-18) * max(np.float32(1e-2), abs(p[idx]))
+        pp, pm = p.copy(), p.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        hp = float(pp[idx]) - float(p[idx])
+        hm = float(p[idx]) - float(pm[idx])
+        lp, _ = oracle.mlp_loss_grad(pp, u, y)
+        lm, _ = oracle.mlp_loss_grad(pm, u, y)
+        fd = (lp - lm) / (hp + hm)
+        assert abs(fd - g[idx]) <= 1e-4 * abs(g[idx]) + 1e-9, (idx, fd, g[idx])
+        checked += 1
+    assert checked > 20
+
+
+def test_gradient_zero_at_perfect_fit_and_sign():
+    """identity network f(u) = u on targets y = u: zero loss, zero gradient;
+    raising the output bias raises the loss with a positive derivative."""
+    p = np.zeros(oracle.MLP_NP, dtype=np.float32)
+    p[oracle.W1] = 1.0
+    p[oracle.W2] = 1.0
+    p[oracle.W3] = 1.0
+    u = np.linspace(0.05, 0.95, 50)
+    loss, g = oracle.mlp_loss_grad(p, u, u)
+    assert loss < 1e-30 and np.abs(g).max() < 1e-15
+    p[oracle.B3] = 0.125
+    loss, g = oracle.mlp_loss_grad(p, u, u)
+    assert abs(loss - 0.125**2) < 1e-15 and abs(g[oracle.B3] - 0.25) < 1e-15
+    # dL/dW3[0] = mean(2 r h2) = 2 * 0.125 * mean(u)
+    assert abs(g[oracle.W3] - 0.25 * u.mean()) < 1e-15
+
+
+def test_tiny_network_closed_form():
+    p = np.zeros(oracle.MLP_NP, dtype=np.float32)
+    p[oracle.W1] = 2.0
+    p[oracle.B1] = -0.5        # h1 = clamp(2u - 0.5)
+    p[oracle.W2] = 1.0         # h2 = h1
+    p[oracle.W3] = 0.5         # f = 0.5 h2 + 0.25
+    p[oracle.B3] = 0.25
+    for u, want in [(0.0, 0.25), (0.25, 0.25), (0.5, 0.5), (0.75, 0.75), (1.0, 0.75)]:
+        assert oracle.mlp_forward(p, u) == want
+    assert oracle.mlp_bucket(p, U64, 0, U64, 4096) == 3072
+
+
+def test_quantile_init_interpolates_the_sample_cdf():
+    keys, _ = synth.make("gmm", 50_000)
+    s = np.sort(keys)
+    smin, smax = int(s[0]), int(s[-1])
+    p = oracle.mlp_init(s, smin, smax)
+    m = s.size
+    for i in range(0, 33):
+        idx = int(i * (m - 1) / 32)
+        q = oracle.mlp_norm(int(s[idx]), smin, smax)
+        f = oracle.mlp_forward(p, q)
+        # f(q_i) = i/32 up to the float32 rounding of W1, b1 and of each
+        # first-layer pre-activation (propagated through W2 = I and W3 = 1/32)
+        # plus the 32 float32 additions of the output sum
+        w1 = p[oracle.W1:oracle.W1 + 32].astype(np.float64)
+        b1 = p[oracle.B1:oracle.B1 + 32].astype(np.float64)
+        tol = ((np.abs(w1) * q + np.abs(b1) + 1).sum() / 32 + 32) * 2.0**-23
+        assert abs(f - i / 32) <= tol, (i, f, tol)
+    assert np.all(p[oracle.W1:oracle.W1 + 32] > 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_monotone_for_nonnegative_weights(seed):
+    p = random_params(seed)
+    us = np.linspace(0, 1, 20001)
+    f = np.array([oracle.mlp_forward(p, float(u)) for u in us])
+    assert np.all(np.diff(f) >= 0)
+
+
+def test_thresholds_are_the_first_keys_of_each_bucket():
+    p = random_params(7, scale=1.0)
+    smin, smax = 10**15, 2**63 + 12345
+    B = 64
+    nt, t = oracle.mlp_thresholds(p, smin, smax, B)
+    assert nt == oracle.mlp_bucket(p, U64, smin, smax, B)
+    assert np.all(np.diff(t[:nt].astype(object)) >= 0)
+    for b in range(1, nt + 1):
+        x = int(t[b - 1])
+        assert oracle.mlp_bucket(p, x, smin, smax, B) >= b
+        if x > 0:
+            assert oracle.mlp_bucket(p, x - 1, smin, smax, B) < b
+    # bucket(x) == #{b : t_b <= x} on random keys
+    rng = np.random.default_rng(0)
+    for x in rng.integers(0, 2**64, size=300, dtype=np.uint64, endpoint=False):
+        direct = oracle.mlp_bucket(p, int(x), smin, smax, B)
+        via = int(np.count_nonzero(t[:nt] <= x))
+        assert direct == via
+
+
+def test_mid_rank_targets():
+    s = np.array([5, 7, 7, 7, 9], dtype=np.uint64)
+    y = oracle.mlp_targets(s)
+    # (#{< x} + #{<= x}) / (2m): the middle of each key's run of ranks
+    assert y.tolist() == [0.1, 0.5, 0.5, 0.5, 0.9]
