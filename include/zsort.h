@@ -233,6 +233,136 @@ typedef struct zsort_kernel_times {
 int zsort_profile_begin(void* stream);
 int zsort_profile_end(void* stream, zsort_kernel_times* out /* host */);
 
+/*
+ * Learned partition map for the first distribution pass (an extension: the
+ * paper's map is Eq. (1); Section III only asks of a map that clusters come
+ * out ordered, max(C_j) <= min(C_j+1), which makes the concatenation of the
+ * sorted clusters sorted).
+ *
+ * A monotone MLP f: [0, 1] -> R, 1 -> 32 -> 32 -> 1, with non-negative
+ * weights and clamp(., 0, 1) activations, approximates the CDF of a 1 %
+ * strided key sample.  Key x goes to cluster
+ *   min(B - 1, floor(B * clamp(f(u(x)), 0, 1))),
+ *   u(x) = 0 if x <= smin, 1 if x >= smax, else (x - smin) / (smax - smin),
+ * smin / smax the sample's extremes.  The first layer (weights, product
+ * and sum) is binary64, its pre-activation rounded once to binary32; the
+ * rest is binary32 with separately rounded products and sums in index order.
+ * The 1153 parameters (W1[32], b1[32], W2[32][32], b2[32], W3[32], b3, in
+ * this order wherever they are indexed, e.g. gradients) are held in a
+ * zsort_mlp_params: binary64 W1 and b1 place a ramp to a small fraction of
+ * its width even where a narrow, heavy component of the keys spans less than
+ * binary32's resolution of the normalised range.
+ *
+ * zsort_stable_learned: (1) samples one key per sample_stride (offset from
+ * SplitMix64 of seed), sorts the sample with the plain path, fits the MLP
+ * (initialisation from the sample: 28 equal-count blocks, the 4 with the
+ * widest internal gaps cut at the gap, one first-layer ramp per piece
+ * weighed by its share of the sample, i.e. the sample CDF linear inside a
+ * piece and flat across gaps; then `steps` Adam steps on the squared error to
+ * the keys' mid-ranks, weights projected onto >= 0, deterministic gradient
+ * reduction; the trained parameters are kept only if the sample's largest
+ * cluster under them is not larger than under the initial ones), and
+ * compiles it into
+ * thresholds t_b = min{x : cluster(x) >= b} by bisection over the 64-bit
+ * keys; (2) runs the first pass with B clusters
+ * (cluster = number of thresholds <= key, found by binary search in LDS;
+ * or, with ZSORT_LEARNED_DIRECT, the MLP evaluated per key); (3) checks on
+ * the device that every non-empty cluster's maximum is <= the minimum of
+ * every later cluster; (4) if the check passes, finishes with the z-score
+ * recursion (children take their exact mean); otherwise sorts the caller's
+ * keys, which the first pass left untouched, with the plain z-score path.
+ * The output is the same stable sort in every case.
+ *
+ * The call is synchronous (it waits for the check).  cfg as for
+ * zsort_stable_ex (ZSORT_FLAG_GRAPH is not supported); lcfg may be NULL
+ * (defaults); report (host) may be NULL.  Arrays too small for a first pass
+ * (n <= cutoff) or for a sample of 64 keys take the plain path
+ * (report->used_learned = 0, report->fallback = 0).
+ */
+#define ZSORT_MLP_PARAMS 1153
+typedef struct zsort_mlp_params {
+  double w1[32], b1[32];           /* first layer, binary64 */
+  float w2[32 * 32], b2[32];       /* second layer, w2[j * 32 + i]: input i -> unit j */
+  float w3[32], b3;                /* output */
+} zsort_mlp_params;
+#define ZSORT_LEARNED_DIRECT 1u       /* per-key MLP inference in the first pass */
+#define ZSORT_LEARNED_ZSCORE_DIAG 2u  /* also count the z-score map's clusters at B */
+typedef struct zsort_learned_config {
+  int32_t buckets;        /* B: clusters of the first pass, 16..4096; default 4096 */
+  int32_t sample_stride;  /* one key per stride is sampled; default 100 (1 %) */
+  int32_t steps;          /* Adam steps, 0 = initialisation only; default 32 */
+  int32_t batches;        /* step t uses samples i with i mod batches == t mod batches; default 64 */
+  double lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8); default 1e-4 */
+  uint64_t seed;          /* sample offsets */
+  uint32_t flags;         /* ZSORT_LEARNED_* */
+  uint32_t reserved;
+  const zsort_mlp_params* params;  /* DEVICE, or NULL to fit on a sample; when given, no
+                                      sample is drawn and smin/smax below are used */
+  uint64_t smin, smax;    /* normalisation range with params (smin <= smax) */
+} zsort_learned_config;
+
+typedef struct zsort_learned_report {
+  int32_t used_learned;          /* 1: the learned map sorted the first pass */
+  int32_t fallback;              /* 1: the order check failed; the z-score path ran */
+  int32_t thresholds;            /* nt (-1 with ZSORT_LEARNED_DIRECT) */
+  int32_t steps;                 /* Adam steps run */
+  int32_t trained;               /* 1: the trained parameters were kept, 0: the initial ones */
+  int32_t reserved;
+  uint32_t sample_max_init;      /* largest cluster of the sample, initial parameters */
+  uint32_t sample_max_trained;   /* the same after training */
+  uint64_t sample_keys;          /* m = n / sample_stride (0 with given params) */
+  uint64_t max_cluster_learned;  /* largest first-pass cluster of the learned map */
+  uint64_t max_cluster_zscore;   /* the same for the z-score map (ZSORT_LEARNED_ZSCORE_DIAG) */
+  double imbalance_learned;      /* max_cluster_learned / (n / B) */
+  double imbalance_zscore;       /* max_cluster_zscore / (n / B), 0 if not measured */
+  double loss_first, loss_last;  /* loss on minibatch 0 before training and of the kept
+                                    parameters */
+  double train_ms;               /* device time: sample, sample sort, fit, thresholds */
+  double first_pass_ms;          /* device time: learned first pass and order check */
+  uint32_t* counts;              /* HOST, B words, or NULL: cluster sizes of the learned first
+                                    pass (set by the caller; left in place) */
+} zsort_learned_report;
+
+int zsort_default_learned_config(zsort_learned_config* lcfg);
+int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                         const zsort_config* cfg, const zsort_learned_config* lcfg,
+                         zsort_learned_report* report, void* stream);
+
+/*
+ * Parity/debug entries of the learned map; all synchronous, all pointers
+ * DEVICE unless noted.
+ *   zsort_learned_sample  out[i] = keys[i * stride + (SplitMix64 offset)],
+ *                         i < n / stride, each offset in [0, stride)
+ *   zsort_mlp_forward     f(u(keys[i])) into f_out and its cluster among
+ *                         `buckets` into cluster_out (either may be NULL)
+ *   zsort_mlp_thresholds  thr_out[b - 1] = t_b for b = 1..nt, 0 after nt
+ *                         (buckets - 1 words); *nt_out (host) = nt
+ *   zsort_mlp_init        the initialisation above from a sorted sample of m
+ *                         keys (range: its first and last key)
+ *   zsort_mlp_grad        gradient of the mean squared error over the whole
+ *                         sorted sample (targets: mid-ranks, inputs: u of
+ *                         the sample's own range) into grad_out[0, 1153) and
+ *                         the loss into grad_out[1153], binary64
+ *   zsort_mlp_train       params (in place) after `steps` Adam steps as in
+ *                         zsort_stable_learned (without its keep-the-better
+ *                         rule); losses_out (host, may be NULL) = the loss
+ *                         of the first and of the last step's minibatch,
+ *                         each before its update
+ */
+int zsort_learned_sample(const uint64_t* keys, size_t n, int32_t stride, uint64_t seed,
+                         uint64_t* out, void* stream);
+int zsort_mlp_forward(const zsort_mlp_params* params, const uint64_t* keys, size_t q, uint64_t smin,
+                      uint64_t smax, int32_t buckets, float* f_out, uint32_t* cluster_out,
+                      void* stream);
+int zsort_mlp_thresholds(const zsort_mlp_params* params, uint64_t smin, uint64_t smax, int32_t buckets,
+                         uint64_t* thr_out, int32_t* nt_out, void* stream);
+int zsort_mlp_init(const uint64_t* sorted_sample, size_t m, zsort_mlp_params* params_out,
+                   void* stream);
+int zsort_mlp_grad(const zsort_mlp_params* params, const uint64_t* sorted_sample, size_t m, double* grad_out,
+                   void* stream);
+int zsort_mlp_train(zsort_mlp_params* params, const uint64_t* sorted_sample, size_t m, int32_t steps,
+                    int32_t batches, double lr, double* losses_out, void* stream);
+
 /* Frees every cached workspace (synchronises the device). */
 int zsort_release(void);
 

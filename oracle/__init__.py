@@ -70,6 +70,8 @@ def lib():
         L.zo_mlp_init.argtypes = [P, U64, U64, U64, P]
         L.zo_mlp_loss_grad.argtypes = [P, P, P, U64, P]
         L.zo_mlp_loss_grad.restype = D
+        L.zo_mlp_train.argtypes = [P, P, P, U64, ctypes.c_uint32, ctypes.c_uint32, D, P]
+        L.zo_mlp_train.restype = D
         assert L.zo_seg_rec_size() == SEG_REC.itemsize
         _lib = L
     return _lib
@@ -226,9 +228,12 @@ MLP_H = 32
 W1, B1, W2, B2, W3, B3 = 0, 32, 64, 1088, 1120, 1152
 
 
-def _f32(p):
-    p = np.ascontiguousarray(p, dtype=np.float32)
+def _par(p):
+    """parameters as the oracle takes them: 1153 doubles, W1 and b1 binary64,
+    the rest rounded to binary32"""
+    p = np.array(p, dtype=np.float64).reshape(-1)
     assert p.size == MLP_NP
+    p[W2:] = p[W2:].astype(np.float32)
     return p
 
 
@@ -237,23 +242,23 @@ def mlp_norm(x: int, smin: int, smax: int) -> float:
 
 
 def mlp_forward(p, u: float) -> float:
-    p = _f32(p)
+    p = _par(p)
     return float(lib().zo_mlp_forward(p.ctypes.data, u))
 
 
 def mlp_bucket(p, x: int, smin: int, smax: int, B: int) -> int:
-    p = _f32(p)
+    p = _par(p)
     return int(lib().zo_mlp_bucket(p.ctypes.data, x, smin, smax, B))
 
 
 def mlp_buckets(p, xs, smin, smax, B):
-    p = _f32(p)
+    p = _par(p)
     f = lib().zo_mlp_bucket
     return np.array([f(p.ctypes.data, int(x), smin, smax, B) for x in xs], dtype=np.int64)
 
 
 def mlp_thresholds(p, smin: int, smax: int, B: int):
-    p = _f32(p)
+    p = _par(p)
     out = np.zeros(B - 1, dtype=np.uint64)
     nt = lib().zo_mlp_thresholds(p.ctypes.data, smin, smax, B, out.ctypes.data)
     return int(nt), out
@@ -261,19 +266,31 @@ def mlp_thresholds(p, smin: int, smax: int, B: int):
 
 def mlp_init(sorted_sample, smin: int, smax: int):
     s = np.ascontiguousarray(sorted_sample, dtype=np.uint64)
-    p = np.zeros(MLP_NP, dtype=np.float32)
+    p = np.zeros(MLP_NP, dtype=np.float64)
     lib().zo_mlp_init(s.ctypes.data, s.size, smin, smax, p.ctypes.data)
     return p
 
 
 def mlp_loss_grad(p, u, y):
-    p = _f32(p)
+    p = _par(p)
     u = np.ascontiguousarray(u, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     g = np.zeros(MLP_NP, dtype=np.float64)
     loss = lib().zo_mlp_loss_grad(p.ctypes.data, u.ctypes.data, y.ctypes.data, u.size,
                                   g.ctypes.data)
     return float(loss), g
+
+
+def mlp_train(p, u, y, steps, batches, lr):
+    """Adam training as the learned form defines it; returns (params, loss of
+    the first step's minibatch, loss of the last step's)."""
+    p = _par(p)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    first = ctypes.c_double(0.0)
+    last = lib().zo_mlp_train(p.ctypes.data, u.ctypes.data, y.ctypes.data, u.size, batches, steps,
+                              lr, ctypes.byref(first))
+    return p, float(first.value), float(last)
 
 
 def mlp_targets(sorted_sample):

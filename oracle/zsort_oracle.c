@@ -587,9 +587,13 @@ int zo_seg_rec_size(void) { return (int)sizeof(zo_seg_rec); }
 /* ====================================================================== */
 /* Learned partition (an extension beyond the paper): a monotone MLP that  */
 /* approximates the keys' CDF and replaces the z-score map at the first    */
-/* pass.  Parameter layout (1153 floats): W1[32] b1[32] W2[32][32] (row =  */
-/* output unit) b2[32] W3[32] b3.  Non-negative weights and clamp ramps    */
-/* make f non-decreasing.                                                  */
+/* pass.  Parameters, 1153 values in this order: W1[32] b1[32] W2[32][32]  */
+/* (row = output unit) b2[32] W3[32] b3.  W1 and b1 are binary64 (a ramp   */
+/* of the first layer must be placed to within a fraction of its width, and */
+/* a narrow, heavy mixture component far from 0 spans ~1e-7 of the        */
+/* normalised range, below binary32's resolution); the rest are binary32  */
+/* values, passed here as doubles that binary32 represents exactly.        */
+/* Non-negative weights and clamp ramps make f non-decreasing.             */
 /* ====================================================================== */
 enum { ZO_H = 32, ZO_NP = 1153, ZO_W1 = 0, ZO_B1 = 32, ZO_W2 = 64, ZO_B2 = 1088, ZO_W3 = 1120,
        ZO_B3 = 1152 };
@@ -604,35 +608,35 @@ double zo_mlp_norm(uint64_t x, uint64_t smin, uint64_t smax)
     return (double)(x - smin) / (double)(smax - smin);
 }
 
-/* Inference in the precision both sides use: the first layer's
- * pre-activation in binary64, rounded to binary32; everything after in
+/* Inference in the precision both sides use: the first layer in binary64
+ * (product, then sum), rounded once to binary32; everything after in
  * binary32, products and sums rounded separately, sums in index order. */
-float zo_mlp_forward(const float *p, double u)
+float zo_mlp_forward(const double *p, double u)
 {
     float h1[ZO_H], h2[ZO_H];
     for (int i = 0; i < ZO_H; i++) {
-        double a = (double)p[ZO_W1 + i] * u;
-        a = a + (double)p[ZO_B1 + i];
+        double a = p[ZO_W1 + i] * u;
+        a = a + p[ZO_B1 + i];
         h1[i] = clamp01f((float)a);
     }
     for (int j = 0; j < ZO_H; j++) {
-        float acc = p[ZO_B2 + j];
+        float acc = (float)p[ZO_B2 + j];
         for (int i = 0; i < ZO_H; i++) {
-            float t = p[ZO_W2 + j * ZO_H + i] * h1[i];
+            float t = (float)p[ZO_W2 + j * ZO_H + i] * h1[i];
             acc = acc + t;
         }
         h2[j] = clamp01f(acc);
     }
-    float f = p[ZO_B3];
+    float f = (float)p[ZO_B3];
     for (int j = 0; j < ZO_H; j++) {
-        float t = p[ZO_W3 + j] * h2[j];
+        float t = (float)p[ZO_W3 + j] * h2[j];
         f = f + t;
     }
     return f;
 }
 
 /* cluster of a key under the learned map with B clusters */
-int zo_mlp_bucket(const float *p, uint64_t x, uint64_t smin, uint64_t smax, int B)
+int zo_mlp_bucket(const double *p, uint64_t x, uint64_t smin, uint64_t smax, int B)
 {
     float f = clamp01f(zo_mlp_forward(p, zo_mlp_norm(x, smin, smax)));
     float t = (float)B * f;
@@ -645,7 +649,7 @@ int zo_mlp_bucket(const float *p, uint64_t x, uint64_t smin, uint64_t smax, int 
  * nt = bucket(2^64 - 1); found by bisection over the u64 keys, which is
  * exact when the map is non-decreasing.  Returns nt; out gets B-1 words
  * (unused ones are 0). */
-int zo_mlp_thresholds(const float *p, uint64_t smin, uint64_t smax, int B, uint64_t *out)
+int zo_mlp_thresholds(const double *p, uint64_t smin, uint64_t smax, int B, uint64_t *out)
 {
     int nt = zo_mlp_bucket(p, UINT64_MAX, smin, smax, B);
     for (int b = 1; b < B; b++) out[b - 1] = 0;
@@ -661,30 +665,79 @@ int zo_mlp_thresholds(const float *p, uint64_t smin, uint64_t smax, int B, uint6
     return nt;
 }
 
-/* Quantile initialisation from the sorted sample s[0, m): unit i ramps from
- * 0 to 1 between the sample's i/32 and (i+1)/32 quantiles; the second layer
- * passes the ramps through; the output averages them.  The result is the
- * piecewise-linear interpolation of the sample's CDF at 33 knots. */
-void zo_mlp_init(const uint64_t *s, uint64_t m, uint64_t smin, uint64_t smax, float *p)
+/* Initialisation from the sorted sample s[0, m) (u = normalised keys).
+ * The sample is cut into ZO_NBLK blocks of equal count; a block whose
+ * largest gap between consecutive keys covers more than half of its key
+ * range is cut at that gap (at most ZO_NSPLIT blocks, those with the largest
+ * gap-to-range ratio, ties to the lower block).  Each piece r of consecutive
+ * sample keys [a, b] gets one unit of the first layer, a ramp from 0 at u[a]
+ * to 1 at u[b] (a step at u[a] when u[a] == u[b]); the second layer passes
+ * the ramps through and the output weighs ramp r by its share (b - a + 1)/m
+ * of the sample.  f is then the sample CDF interpolated linearly inside each
+ * piece and flat between pieces, so a gap between two mixture components
+ * gets no clusters.  Unused units stay 0. */
+enum { ZO_NBLK = 28, ZO_NSPLIT = 4 };
+
+void zo_mlp_init(const uint64_t *s, uint64_t m, uint64_t smin, uint64_t smax, double *p)
 {
-    for (int i = 0; i < ZO_NP; i++) p[i] = 0.0f;
-    double q[ZO_H + 1];
-    for (int i = 0; i <= ZO_H; i++) {
-        uint64_t idx = (uint64_t)(((double)i * (double)(m - 1)) / (double)ZO_H);
-        q[i] = zo_mlp_norm(s[idx], smin, smax);
+    for (int i = 0; i < ZO_NP; i++) p[i] = 0.0;
+    uint64_t lo[ZO_NBLK + 1];
+    for (int i = 0; i <= ZO_NBLK; i++) lo[i] = ((uint64_t)i * m) / ZO_NBLK;
+    double score[ZO_NBLK];
+    uint64_t cut[ZO_NBLK];
+    for (int i = 0; i < ZO_NBLK; i++) {
+        score[i] = 0.0;
+        cut[i] = 0;
+        uint64_t a = lo[i], b = lo[i + 1];
+        if (b - a < 2) continue;
+        double span = zo_mlp_norm(s[b - 1], smin, smax) - zo_mlp_norm(s[a], smin, smax);
+        if (!(span > 0.0)) continue;
+        double gmax = -1.0;
+        for (uint64_t j = a; j + 1 < b; j++) {
+            double g = zo_mlp_norm(s[j + 1], smin, smax) - zo_mlp_norm(s[j], smin, smax);
+            if (g > gmax) { gmax = g; cut[i] = j; }
+        }
+        score[i] = gmax / span;
     }
-    for (int i = 0; i < ZO_H; i++) {
-        double w = q[i + 1] > q[i] ? 1.0 / (q[i + 1] - q[i]) : 1.0e6;
-        p[ZO_W1 + i] = (float)w;
-        p[ZO_B1 + i] = (float)(-q[i] * w);
-        p[ZO_W2 + i * ZO_H + i] = 1.0f;
-        p[ZO_W3 + i] = 1.0f / (float)ZO_H;
+    int split[ZO_NBLK];
+    for (int i = 0; i < ZO_NBLK; i++) split[i] = 0;
+    for (int k = 0; k < ZO_NSPLIT; k++) {
+        int best = -1;
+        for (int i = 0; i < ZO_NBLK; i++)
+            if (!split[i] && score[i] > 0.5 && (best < 0 || score[i] > score[best])) best = i;
+        if (best < 0) break;
+        split[best] = 1;
+    }
+    int r = 0;
+    for (int i = 0; i < ZO_NBLK; i++) {
+        uint64_t a = lo[i], b = lo[i + 1];
+        if (a == b) continue;
+        uint64_t piece[2][2];
+        int np_ = 0;
+        if (split[i]) {
+            piece[0][0] = a; piece[0][1] = cut[i];
+            piece[1][0] = cut[i] + 1; piece[1][1] = b - 1;
+            np_ = 2;
+        } else {
+            piece[0][0] = a; piece[0][1] = b - 1;
+            np_ = 1;
+        }
+        for (int q = 0; q < np_; q++, r++) {
+            double ua = zo_mlp_norm(s[piece[q][0]], smin, smax);
+            double ub = zo_mlp_norm(s[piece[q][1]], smin, smax);
+            double w = ub > ua ? 1.0 / (ub - ua) : 4503599627370496.0;  /* 2^52: a step */
+            p[ZO_W1 + r] = w;
+            p[ZO_B1 + r] = -ua * w;
+            p[ZO_W2 + r * ZO_H + r] = 1.0;
+            p[ZO_W3 + r] = (double)(float)((double)(piece[q][1] - piece[q][0] + 1) / (double)m);
+        }
     }
 }
 
 /* Mean squared error over (u[s], y[s]) and its exact gradient in binary64
- * (the clamp's derivative is 1 strictly inside (0, 1), else 0). */
-double zo_mlp_loss_grad(const float *p, const double *u, const double *y, uint64_t m, double *g)
+ * (the clamp's derivative is 1 strictly inside (0, 1), else 0); binary32
+ * parameters enter as the doubles they are. */
+double zo_mlp_loss_grad(const double *p, const double *u, const double *y, uint64_t m, double *g)
 {
     double W1[ZO_H], b1[ZO_H], W2[ZO_H][ZO_H], b2[ZO_H], W3[ZO_H], b3 = p[ZO_B3];
     for (int i = 0; i < ZO_H; i++) {
@@ -729,4 +782,45 @@ double zo_mlp_loss_grad(const float *p, const double *u, const double *y, uint64
         }
     }
     return loss;
+}
+
+/* Training of the map: Adam (Kingma and Ba, "Adam: A Method for Stochastic
+ * Optimization", ICLR 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and
+ * bias correction, on the mean squared error of minibatch j = t mod nb
+ * (samples j, j + nb, j + 2nb, ...) at step t; exact binary64 gradients;
+ * W1 and b1 stay binary64, every other parameter is rounded to binary32
+ * after each step; weights (not biases) are projected onto >= 0.
+ * Returns the loss of the last step's minibatch (before its update);
+ * *loss_first gets the first step's. */
+double zo_mlp_train(double *p, const double *u, const double *y, uint64_t m, uint32_t nb,
+                    uint32_t steps, double lr, double *loss_first)
+{
+    double m1[ZO_NP], m2[ZO_NP], g[ZO_NP];
+    for (int i = 0; i < ZO_NP; i++) m1[i] = m2[i] = 0.0;
+    double *ub = (double *)malloc(sizeof(double) * (m / nb + 1));
+    double *yb = (double *)malloc(sizeof(double) * (m / nb + 1));
+    double b1p = 1.0, b2p = 1.0, last = 0.0;
+    for (uint32_t t = 0; t < steps; t++) {
+        uint32_t j = t % nb;
+        uint64_t c = 0;
+        for (uint64_t i = j; i < m; i += nb) { ub[c] = u[i]; yb[c] = y[i]; c++; }
+        double loss = c ? zo_mlp_loss_grad(p, ub, yb, c, g) : 0.0;
+        if (t == 0 && loss_first) *loss_first = loss;
+        last = loss;
+        b1p = b1p * 0.9;
+        b2p = b2p * 0.999;
+        for (int i = 0; i < ZO_NP; i++) {
+            m1[i] = 0.9 * m1[i] + (1.0 - 0.9) * g[i];
+            m2[i] = 0.999 * m2[i] + (1.0 - 0.999) * (g[i] * g[i]);
+            double mh = m1[i] / (1.0 - b1p);
+            double vh = m2[i] / (1.0 - b2p);
+            double pn = p[i] - (lr * mh) / (sqrt(vh) + 1e-8);
+            int weight = (i < ZO_B1) || (i >= ZO_W2 && i < ZO_B2) || (i >= ZO_W3 && i < ZO_B3);
+            if (weight && !(pn > 0.0)) pn = 0.0;
+            p[i] = i < ZO_W2 ? pn : (double)(float)pn;
+        }
+    }
+    free(ub);
+    free(yb);
+    return last;
 }

@@ -24,8 +24,15 @@ EXPORTED = [
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
     "zsort_strerror", "zsort_profile_begin", "zsort_profile_end", "zsort_autotune",
+    "zsort_default_learned_config", "zsort_stable_learned", "zsort_learned_sample",
+    "zsort_mlp_forward", "zsort_mlp_thresholds", "zsort_mlp_init", "zsort_mlp_grad",
+    "zsort_mlp_train",
 ]
 ZSORT_FLAG_GRAPH = 1
+ZSORT_MLP_PARAMS = 1153
+MLP_PARAMS_BYTES = 4872   # sizeof(zsort_mlp_params): 64 binary64, 1089 binary32, padding
+ZSORT_LEARNED_DIRECT = 1
+ZSORT_LEARNED_ZSCORE_DIAG = 2
 STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
 
 
@@ -46,6 +53,27 @@ class ZsortStats(ctypes.Structure):
                 ("segs_per_level", ctypes.c_uint32 * MAX_LEVELS),
                 ("local_keys", ctypes.c_uint64),
                 ("model_bytes", ctypes.c_double)]
+
+
+class ZsortLearnedConfig(ctypes.Structure):
+    _fields_ = [("buckets", ctypes.c_int32), ("sample_stride", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("batches", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("params", ctypes.c_void_p), ("smin", ctypes.c_uint64),
+                ("smax", ctypes.c_uint64)]
+
+
+class ZsortLearnedReport(ctypes.Structure):
+    _fields_ = [("used_learned", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("thresholds", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("trained", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sample_max_init", ctypes.c_uint32), ("sample_max_trained", ctypes.c_uint32),
+                ("sample_keys", ctypes.c_uint64), ("max_cluster_learned", ctypes.c_uint64),
+                ("max_cluster_zscore", ctypes.c_uint64), ("imbalance_learned", ctypes.c_double),
+                ("imbalance_zscore", ctypes.c_double), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("train_ms", ctypes.c_double),
+                ("first_pass_ms", ctypes.c_double), ("counts", ctypes.c_void_p)]
 
 
 class ZsortKernelTimes(ctypes.Structure):
@@ -92,6 +120,16 @@ def lib():
         L.zsort_autotune.argtypes = [P, P, I, Z, P, ctypes.c_int32, ctypes.c_char_p, P, P]
         L.zsort_profile_begin.argtypes = [P]
         L.zsort_profile_end.argtypes = [P, P]
+        U64 = ctypes.c_uint64
+        L.zsort_default_learned_config.argtypes = [P]
+        L.zsort_stable_learned.argtypes = [P, P, I, Z, P, P, P, P]
+        L.zsort_learned_sample.argtypes = [P, Z, ctypes.c_int32, U64, P, P]
+        L.zsort_mlp_forward.argtypes = [P, P, Z, U64, U64, ctypes.c_int32, P, P, P]
+        L.zsort_mlp_thresholds.argtypes = [P, U64, U64, ctypes.c_int32, P, P, P]
+        L.zsort_mlp_init.argtypes = [P, Z, P, P]
+        L.zsort_mlp_grad.argtypes = [P, P, Z, P, P]
+        L.zsort_mlp_train.argtypes = [P, P, Z, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      P, P]
         L.zsort_strerror.argtypes = [I]
         L.zsort_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -257,6 +295,133 @@ def zsort_profile_end(stream=None) -> dict:
 
 def zsort_release():
     _check("zsort_release", lib().zsort_release())
+
+
+def _dptr(t, dtype, n=None, name="tensor"):
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or (n is not None and t.numel() != n):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor"
+                         + ("" if n is None else f" of {n} elements"))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_pack(flat) -> np.ndarray:
+    """1153 parameter values (W1, b1, W2, b2, W3, b3) -> the bytes of a
+    zsort_mlp_params (W1, b1 binary64; the rest rounded to binary32)."""
+    flat = np.asarray(flat, dtype=np.float64).reshape(-1)
+    if flat.size != ZSORT_MLP_PARAMS:
+        raise ValueError("expected 1153 parameters")
+    buf = flat[:64].astype("<f8").tobytes() + flat[64:].astype("<f4").tobytes() + bytes(4)
+    return np.frombuffer(buf, dtype=np.uint8).copy()
+
+
+def mlp_unpack(buf) -> np.ndarray:
+    """bytes of a zsort_mlp_params -> the 1153 parameter values as float64"""
+    b = np.asarray(buf, dtype=np.uint8).reshape(-1)
+    if b.size != MLP_PARAMS_BYTES:
+        raise ValueError("expected the bytes of one zsort_mlp_params")
+    return np.concatenate([b[:512].view("<f8"), b[512:512 + 4 * 1089].view("<f4").astype(np.float64)])
+
+
+def _pptr(params):
+    import torch
+    return _dptr(params, torch.uint8, MLP_PARAMS_BYTES, "params (zsort_mlp_params bytes)")
+
+
+def zsort_default_learned_config(**overrides) -> ZsortLearnedConfig:
+    c = ZsortLearnedConfig()
+    _check("zsort_default_learned_config", lib().zsort_default_learned_config(ctypes.byref(c)))
+    for k, v in overrides.items():
+        if k == "params":
+            c.params = _pptr(v).value
+        elif k == "lr":
+            c.lr = float(v)
+        else:
+            setattr(c, k, int(v))
+    return c
+
+
+def zsort_stable_learned(keys, payload=None, cfg=None, lcfg=None, counts=False, stream=None):
+    """Sort with the learned first-pass map; returns the report as a dict
+    (with the first-pass cluster sizes under "counts" when counts=True)."""
+    p, pw = _pay(payload, keys.numel())
+    if isinstance(lcfg, dict):
+        lcfg = zsort_default_learned_config(**lcfg)
+    rep = ZsortLearnedReport()
+    buckets = lcfg.buckets if lcfg is not None else 4096
+    cbuf = np.zeros(buckets, dtype=np.uint32) if counts else None
+    if cbuf is not None:
+        rep.counts = cbuf.ctypes.data
+    _check("zsort_stable_learned", lib().zsort_stable_learned(
+        _keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg),
+        None if lcfg is None else ctypes.byref(lcfg), ctypes.byref(rep), _stream(stream)))
+    out = {f: getattr(rep, f) for f, _ in ZsortLearnedReport._fields_
+           if f not in ("counts", "reserved")}
+    if cbuf is not None:
+        out["counts"] = cbuf
+    return out
+
+
+def zsort_learned_sample(keys, stride=100, seed=0x5A17, stream=None):
+    import torch
+    m = keys.numel() // stride
+    out = torch.empty(max(m, 1), dtype=keys.dtype, device=keys.device)
+    _check("zsort_learned_sample", lib().zsort_learned_sample(
+        _keys_ptr(keys), keys.numel(), stride, seed, ctypes.c_void_p(out.data_ptr()),
+        _stream(stream)))
+    return out[:m]
+
+
+def zsort_mlp_forward(params, keys, smin, smax, buckets=4096, stream=None):
+    """(f, cluster) of every key under the MLP with the given parameters."""
+    import torch
+    q = keys.numel()
+    f = torch.empty(max(q, 1), dtype=torch.float32, device=keys.device)
+    c = torch.empty(max(q, 1), dtype=torch.int32, device=keys.device)
+    _check("zsort_mlp_forward", lib().zsort_mlp_forward(
+        _pptr(params), _keys_ptr(keys), q, smin, smax,
+        buckets, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(c.data_ptr()), _stream(stream)))
+    return f[:q], c[:q]
+
+
+def zsort_mlp_thresholds(params, smin, smax, buckets=4096, stream=None):
+    """(nt, thresholds[buckets - 1]) as a host array of u64."""
+    import torch
+    thr = torch.empty(buckets - 1, dtype=torch.int64, device=params.device)
+    nt = ctypes.c_int32(0)
+    _check("zsort_mlp_thresholds", lib().zsort_mlp_thresholds(
+        _pptr(params), smin, smax, buckets,
+        ctypes.c_void_p(thr.data_ptr()), ctypes.byref(nt), _stream(stream)))
+    return int(nt.value), thr.cpu().numpy().view(np.uint64)
+
+
+def zsort_mlp_init(sorted_sample, stream=None):
+    import torch
+    par = torch.empty(MLP_PARAMS_BYTES, dtype=torch.uint8, device=sorted_sample.device)
+    _check("zsort_mlp_init", lib().zsort_mlp_init(
+        _keys_ptr(sorted_sample), sorted_sample.numel(), ctypes.c_void_p(par.data_ptr()),
+        _stream(stream)))
+    return par
+
+
+def zsort_mlp_grad(params, sorted_sample, stream=None):
+    """(loss, gradient[1153]) over the whole sorted sample, float64 host values."""
+    import torch
+    g = torch.empty(ZSORT_MLP_PARAMS + 1, dtype=torch.float64, device=params.device)
+    _check("zsort_mlp_grad", lib().zsort_mlp_grad(
+        _pptr(params), _keys_ptr(sorted_sample),
+        sorted_sample.numel(), ctypes.c_void_p(g.data_ptr()), _stream(stream)))
+    gh = g.cpu().numpy()
+    return float(gh[-1]), gh[:-1]
+
+
+def zsort_mlp_train(params, sorted_sample, steps, batches=64, lr=1e-3, stream=None):
+    """Trains params (in place); returns (first, last) minibatch loss."""
+    import torch
+    losses = np.zeros(2, dtype=np.float64)
+    _check("zsort_mlp_train", lib().zsort_mlp_train(
+        _pptr(params), _keys_ptr(sorted_sample),
+        sorted_sample.numel(), steps, batches, lr, losses.ctypes.data, _stream(stream)))
+    return float(losses[0]), float(losses[1])
 
 
 def sort(keys, payload=None, cfg=None, stream=None):

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libzsort.so")
-SOURCES = [os.path.join(CSRC, "zsort_kernels.hip"), os.path.join(CSRC, "zsort_api.cpp")]
+SOURCES = [os.path.join(CSRC, "zsort_kernels.hip"), os.path.join(CSRC, "zsort_learned.hip"),
+           os.path.join(CSRC, "zsort_api.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

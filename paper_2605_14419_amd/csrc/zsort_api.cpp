@@ -23,6 +23,32 @@ hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, 
                                 hipStream_t st);
 hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st);
 int stage_blocks_per_cu(int k, int pw, int tile, int stage);
+// learned partition map (zsort_learned.hip)
+hipError_t launch_init_learned(const Ws& ws, uint64_t n, hipStream_t st);
+hipError_t launch_lsample(const uint64_t* x, uint64_t m, uint32_t stride, uint64_t seed,
+                          uint64_t* out, hipStream_t st);
+hipError_t launch_lprep(const uint64_t* s, uint64_t m, double* U, float* Y, LRes* res,
+                        hipStream_t st);
+hipError_t launch_lset_range(LRes* res, uint64_t smin, uint64_t smax, hipStream_t st);
+hipError_t launch_linit(const uint64_t* s, uint64_t m, MlpP* par, hipStream_t st);
+hipError_t launch_ladam_reset(double* adam, LRes* res, hipStream_t st);
+size_t lpart_floats(uint64_t m, uint32_t nb);
+hipError_t launch_ltrain(const double* U, const float* Y, uint64_t m, uint32_t nb, uint32_t step,
+                         MlpP* par, double* adam, float* part, LRes* res, double lr, int mode,
+                         double* gout, hipStream_t st);
+hipError_t launch_lthresh(const MlpP* par, int B, LRes* res, uint64_t* thr, hipStream_t st);
+hipError_t launch_lhist_sample(const double* U, uint64_t m, const MlpP* par, int B,
+                               uint32_t* counts, hipStream_t st);
+hipError_t launch_lkeep(MlpP* par, const MlpP* par0, const double* g0, const double* g1,
+                        const uint32_t* hc0, const uint32_t* hc1, int B, LRes* res,
+                        hipStream_t st);
+hipError_t launch_lforward(const MlpP* par, const uint64_t* x, uint64_t q, const LRes* res, int B,
+                           float* fout, uint32_t* cout, hipStream_t st);
+hipError_t launch_lcheck(const uint64_t* y, const uint32_t* bst, uint64_t n, int B, uint64_t* bmin,
+                         uint64_t* bmax, LRes* res, int grid, hipStream_t st);
+hipError_t launch_lmaxcount(const uint32_t* bst, uint64_t n, int B, uint64_t* out, hipStream_t st);
+hipError_t launch_lcounts(const uint32_t* bst, uint64_t n, int B, uint32_t* counts,
+                          hipStream_t st);
 }  // namespace zs
 
 namespace {
@@ -32,11 +58,12 @@ using zs::Ws;
 struct Shape {
   uint64_t n = 0;
   int pw = 0, k = 0, cutoff = 0, chunk = 0, tile = 0;
+  int kfirst = 0;  // clusters of a learned first pass (0: none)
   int64_t nseg = 0;
   int64_t trace_cap = 0, trace_hist_cap = 0;
   bool operator==(const Shape& o) const {
     return n == o.n && pw == o.pw && k == o.k && cutoff == o.cutoff && chunk == o.chunk &&
-           tile == o.tile &&
+           tile == o.tile && kfirst == o.kfirst &&
            nseg == o.nseg && trace_cap == o.trace_cap && trace_hist_cap == o.trace_hist_cap;
   }
 };
@@ -46,6 +73,7 @@ struct Layout {
       off_hard[2],
       off_status, off_part,
       off_bstart, off_trace, off_thist, total;
+  size_t status_bytes;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap;
 };
 
@@ -82,9 +110,12 @@ Layout plan(const Shape& s) {
     L.off_leavesw[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_hard[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
-  L.off_status = take(status_cap * (size_t)s.k * 8);
+  // look-back words: [slot][k]; a learned first pass has one root of
+  // nchunks slots with kfirst clusters each
+  L.status_bytes = std::max<size_t>(status_cap * (size_t)s.k, (nchunks + 1) * (size_t)s.kfirst) * 8;
+  L.off_status = take(L.status_bytes);
   L.off_part = take(work_cap * 10 * 8);
-  L.off_bstart = take(seg_cap * (size_t)s.k * 4);
+  L.off_bstart = take(std::max<size_t>(seg_cap * (size_t)s.k, (size_t)s.kfirst) * 4);
   L.off_trace = take((size_t)s.trace_cap * sizeof(zs::TraceRec));
   L.off_thist = take((size_t)s.trace_hist_cap * 4);
   L.total = align_up(o, 256);
@@ -128,6 +159,8 @@ struct Workspace {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_stage;  // stage of each (start, end) pair
+  // extra algorithmic bytes of the last call (learned first pass)
+  double last_extra_bytes = 0.0;
   // graph mode
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -164,6 +197,7 @@ hipError_t stage(Workspace* w, const Ws& ws, int L, int st_id, int grid, hipStre
 
 std::mutex g_mu;
 std::unordered_map<hipStream_t, Workspace*> g_ws;
+std::unordered_map<hipStream_t, Workspace*> g_ws_aux;  // sorts of the learned map's key sample
 int g_last_hip = 0;
 int g_cu_count = 0;
 
@@ -202,7 +236,7 @@ int levels_for(const zsort_config& c) {
 }
 
 // Finds (or grows) the stream's workspace and lays it out for `s`.
-int acquire(hipStream_t st, const Shape& s, Workspace** out) {
+int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
@@ -210,7 +244,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out) {
     e = hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e);
   }
-  Workspace*& w = g_ws[st];
+  Workspace*& w = slot ? g_ws_aux[st] : g_ws[st];
   if (!w) w = new Workspace();
   if (w->device != -1 && w->device != dev) return ZSORT_EINVAL;  // stream of another device
   const Layout L = plan(s);
@@ -234,7 +268,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out) {
       if (e != hipSuccess) return hip_fail(e);
     }
     // fresh look-back region: no stale word may carry a live tag
-    e = hipMemsetAsync(w->base + L.off_status, 0, (size_t)L.status_cap * (size_t)s.k * 8, st);
+    e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
     if (e != hipSuccess) return hip_fail(e);
     w->device = dev;
     w->shape = s;
@@ -243,7 +277,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out) {
     w->calls = 0;
   } else if (w->calls && (w->calls % 65536u) == 0) {
     if (capturing(st)) return ZSORT_ECAPTURE;
-    e = hipMemsetAsync(w->base + L.off_status, 0, (size_t)L.status_cap * (size_t)s.k * 8, st);
+    e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   *out = w;
@@ -316,6 +350,8 @@ struct Call {
   zsort_config cfg;
   int64_t trace_cap, hist_cap;
   bool level0_only;
+  int slot = 0;    // 1: the auxiliary workspace (sample sorts of the learned map)
+  int kfirst = 0;  // clusters of a learned first pass the workspace must also hold
 };
 
 // pinned count buffer and per-level events, created once per workspace
@@ -348,8 +384,9 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   s.nseg = c.off ? c.nseg : 0;
   s.trace_cap = c.trace_cap;
   s.trace_hist_cap = c.hist_cap;
+  s.kfirst = c.kfirst;
   Workspace* w = nullptr;
-  int rc = acquire(st, s, &w);
+  int rc = acquire(st, s, &w, c.slot);
   if (rc) return rc;
   const Ws ws = make_ws(w, c.keys, c.pay, c.cfg, c.pw);
   hipError_t e = hipSuccess;
@@ -392,9 +429,12 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   w->last_n = c.n;
   w->last_pw = c.pw;
   w->has_last = true;
+  w->last_extra_bytes = 0.0;
   if (wout) *wout = w;
   return ZSORT_OK;
 }
+
+hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0);
 
 // the launch sequence of one sort on stream st
 hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
@@ -403,6 +443,14 @@ hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
     if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
     else e = zs::launch_init_single(ws, c.n, st);
   }
+  if (e != hipSuccess) return e;
+  return enqueue_levels(w, ws, c, st, 0);
+}
+
+// levels L0, L0 + 1, ... (L0 > 0: level L0 - 1 ran already and recorded its
+// pacing event and segment count)
+hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0) {
+  hipError_t e = hipSuccess;
   const int levels = c.level0_only ? 1 : levels_for(c.cfg);
   // Pacing: level L >= 2 is launched only if level L-1 holds segments, which
   // the host learns from a copy of the count taken after level L-2.  The host
@@ -410,7 +458,7 @@ hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
   // ahead of the device.  Under stream capture every level is launched (each
   // kernel of an empty level exits at once).
   const bool paced = !c.level0_only && !capturing(st) && pacing_ready(w);
-  for (int L = 0; L < levels && e == hipSuccess; ++L) {
+  for (int L = L0; L < levels && e == hipSuccess; ++L) {
     if (paced && L >= 2) {
       e = hipEventSynchronize(w->lvl_ev[L - 2]);
       if (e != hipSuccess) break;
@@ -492,6 +540,139 @@ int common_checks(const uint64_t* keys, const void* pay, int pw, size_t n) {
   return ZSORT_OK;
 }
 
+
+// ---- learned partition map ------------------------------------------------
+struct LearnedWs {
+  int device = -1;
+  char* base = nullptr;
+  size_t bytes = 0;
+  uint64_t n_cap = 0, m_cap = 0;
+  size_t part_cap = 0;
+  uint64_t* sample = nullptr;
+  double* U = nullptr;
+  float* Y = nullptr;
+  zs::MlpP* par = nullptr;
+  zs::MlpP* par0 = nullptr;  // initial parameters, restored if training does not help
+  double* adam = nullptr;
+  float* part = nullptr;
+  uint64_t* thr = nullptr;
+  uint16_t* ids = nullptr;
+  uint64_t* bmin = nullptr;
+  uint64_t* bmax = nullptr;
+  zs::LRes* res = nullptr;
+  double* gout = nullptr;
+  double* gout1 = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t* hc = nullptr;  // sample cluster sizes: [0] initial, [1] trained parameters
+  zs::LRes* h_res = nullptr;  // pinned
+  hipEvent_t ev[5] = {};
+};
+std::unordered_map<hipStream_t, LearnedWs*> g_lws;
+
+// buffers of the learned map for n keys, m sample keys and the partial sums
+// of a training step; grows (and never shrinks) per stream
+int lacquire(hipStream_t st, uint64_t n, uint64_t m, size_t part_floats, LearnedWs** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  LearnedWs*& w = g_lws[st];
+  if (!w) w = new LearnedWs();
+  if (w->device != -1 && w->device != dev) return ZSORT_EINVAL;
+  w->device = dev;
+  if (!w->h_res) {
+    void* p = nullptr;
+    e = hipHostMalloc(&p, sizeof(zs::LRes), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e);
+    w->h_res = (zs::LRes*)p;
+  }
+  for (int i = 0; i < 5; ++i)
+    if (!w->ev[i]) {
+      e = hipEventCreate(&w->ev[i]);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  if (w->base && n <= w->n_cap && m <= w->m_cap && part_floats <= w->part_cap) {
+    *out = w;
+    return ZSORT_OK;
+  }
+  if (capturing(st)) return ZSORT_ECAPTURE;
+  n = std::max(n, w->n_cap);
+  m = std::max<uint64_t>(std::max(m, w->m_cap), 1);
+  part_floats = std::max<size_t>(std::max(part_floats, w->part_cap), zs::kNP + 1);
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = align_up(o, 256);
+    o = at + b;
+    return at;
+  };
+  const size_t o_res = take(sizeof(zs::LRes)), o_par = take(sizeof(zs::MlpP)),
+               o_par0 = take(sizeof(zs::MlpP)), o_adam = take(2 * zs::kNP * 8),
+               o_gout = take((zs::kNP + 1) * 8), o_gout1 = take((zs::kNP + 1) * 8),
+               o_thr = take(zs::kKMax * 8), o_bmin = take(zs::kKMax * 8),
+               o_bmax = take(zs::kKMax * 8), o_cnt = take(zs::kKMax * 4),
+               o_hc = take(2 * zs::kKMax * 4), o_smp = take(m * 8),
+               o_u = take(m * 8), o_y = take(m * 4), o_part = take(part_floats * 4),
+               o_ids = take(std::max<uint64_t>(n, 1) * 2);
+  const size_t total = align_up(o, 256);
+  if (w->base) {
+    e = hipFree(w->base);
+    w->base = nullptr;
+    w->bytes = 0;
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  void* p = nullptr;
+  e = hipMalloc(&p, total);
+  if (e != hipSuccess) return hip_fail(e);
+  char* b = (char*)p;
+  w->base = b;
+  w->bytes = total;
+  w->n_cap = n;
+  w->m_cap = m;
+  w->part_cap = part_floats;
+  w->res = (zs::LRes*)(b + o_res);
+  w->par = (zs::MlpP*)(b + o_par);
+  w->par0 = (zs::MlpP*)(b + o_par0);
+  w->adam = (double*)(b + o_adam);
+  w->gout = (double*)(b + o_gout);
+  w->gout1 = (double*)(b + o_gout1);
+  w->thr = (uint64_t*)(b + o_thr);
+  w->bmin = (uint64_t*)(b + o_bmin);
+  w->bmax = (uint64_t*)(b + o_bmax);
+  w->counts = (uint32_t*)(b + o_cnt);
+  w->hc = (uint32_t*)(b + o_hc);
+  w->sample = (uint64_t*)(b + o_smp);
+  w->U = (double*)(b + o_u);
+  w->Y = (float*)(b + o_y);
+  w->part = (float*)(b + o_part);
+  w->ids = (uint16_t*)(b + o_ids);
+  e = hipMemsetAsync(w->res, 0, sizeof(zs::LRes), st);
+  if (e != hipSuccess) return hip_fail(e);
+  *out = w;
+  return ZSORT_OK;
+}
+
+int check_lcfg(const zsort_learned_config* L) {
+  if (L->buckets < 16 || L->buckets > zs::kKMax) return ZSORT_EINVAL;
+  if (L->sample_stride < 1 || L->steps < 0 || L->steps > 1000000 || L->batches < 1)
+    return ZSORT_EINVAL;
+  if (!(L->lr > 0.0) || !(L->lr < 1e6)) return ZSORT_EINVAL;
+  if (L->params && L->smin > L->smax) return ZSORT_EINVAL;
+  if (L->flags & ~(uint32_t)(ZSORT_LEARNED_DIRECT | ZSORT_LEARNED_ZSCORE_DIAG)) return ZSORT_EINVAL;
+  return ZSORT_OK;
+}
+
+// Ws of the learned first pass: B clusters, thresholds (or per-key MLP)
+Ws first_pass_ws(const Ws& ws, const LearnedWs* lw, int B, bool direct) {
+  Ws w0 = ws;
+  w0.p.k = B;
+  w0.p.lb = floor_log2(B);
+  if (B > 1024) w0.p.tile = 2048;
+  w0.lm.thr = lw->thr;
+  w0.lm.par = lw->par;
+  w0.lm.ids = lw->ids;
+  w0.lm.res = lw->res;
+  w0.lm.direct = direct ? 1 : 0;
+  return w0;
+}
 }  // namespace
 
 extern "C" {
@@ -590,7 +771,7 @@ int zsort_get_last_stats(void* stream, zsort_stats* out) {
     if (ctl.lvl_mkeys[L]) levels = L + 1;
     bytes += 8.0 * (double)ctl.lvl_mkeys[L] + (8.0 + 2 * kp) * (double)ctl.lvl_keys[L];
   }
-  bytes += 2 * kp * (double)ctl.local_keys;
+  bytes += 2 * kp * (double)ctl.local_keys + w->last_extra_bytes;
   out->local_keys = ctl.local_keys;
   out->levels = levels;
   out->model_bytes = bytes;
@@ -773,19 +954,336 @@ int zsort_profile_end(void* stream, zsort_kernel_times* out) {
 int zsort_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = ZSORT_OK;
-  for (auto& kv : g_ws) {
+  auto free_ws = [&](Workspace* w) {
+    drop_graphs(w);
+    if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
+    if (w->base) {
+      hipError_t e = hipFree(w->base);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    for (hipEvent_t ev : w->ev_pool) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : w->lvl_ev)
+      if (ev) (void)hipEventDestroy(ev);
+    if (w->h_nseg) (void)hipHostFree(w->h_nseg);
+    delete w;
+  };
+  for (auto& kv : g_ws) free_ws(kv.second);
+  g_ws.clear();
+  for (auto& kv : g_ws_aux) free_ws(kv.second);
+  g_ws_aux.clear();
+  for (auto& kv : g_lws) {
     if (kv.second->base) {
       hipError_t e = hipFree(kv.second->base);
       if (e != hipSuccess) rc = hip_fail(e);
     }
-    for (hipEvent_t ev : kv.second->ev_pool) (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : kv.second->lvl_ev)
+    if (kv.second->h_res) (void)hipHostFree(kv.second->h_res);
+    for (hipEvent_t ev : kv.second->ev)
       if (ev) (void)hipEventDestroy(ev);
-    if (kv.second->h_nseg) (void)hipHostFree(kv.second->h_nseg);
     delete kv.second;
   }
-  g_ws.clear();
+  g_lws.clear();
   return rc;
+}
+
+
+static_assert(sizeof(zsort_mlp_params) == sizeof(zs::MlpP), "parameter layout");
+
+int zsort_default_learned_config(zsort_learned_config* lcfg) {
+  if (!lcfg) return ZSORT_EINVAL;
+  std::memset(lcfg, 0, sizeof *lcfg);
+  lcfg->buckets = 4096;
+  lcfg->sample_stride = 100;
+  lcfg->steps = 32;
+  lcfg->batches = 64;
+  lcfg->lr = 1e-4;
+  lcfg->seed = 0x5A17ull;
+  return ZSORT_OK;
+}
+
+int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                         const zsort_config* cfg, const zsort_learned_config* lcfg,
+                         zsort_learned_report* report, void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  zsort_learned_config L;
+  zsort_default_learned_config(&L);
+  if (lcfg) L = *lcfg;
+  rc = check_lcfg(&L);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c, n, payload_bytes, 0);
+  if (rc) return rc;
+  if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
+  uint32_t* host_counts = report ? report->counts : nullptr;
+  if (report) {
+    std::memset(report, 0, sizeof *report);
+    report->counts = host_counts;
+  }
+  if (n <= 1) return ZSORT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (capturing(st)) return ZSORT_ECAPTURE;
+  void* pay = payload_bytes ? payload : nullptr;
+  Call call{keys, pay, payload_bytes, (uint64_t)n, nullptr, 0, c, 0, 0, false};
+  const int B = L.buckets;
+  const uint64_t m = L.params ? 0 : (uint64_t)n / (uint64_t)L.sample_stride;
+  if ((uint64_t)n <= (uint64_t)c.cutoff || (!L.params && m < 64)) {
+    // too small for a first pass of its own, or for a sample: the plain path
+    return run(call, st, nullptr);
+  }
+  const uint32_t nb = (uint32_t)L.batches;
+  LearnedWs* lw = nullptr;
+  rc = lacquire(st, n, m, m ? zs::lpart_floats(m, nb) : 0, &lw);
+  if (rc) return rc;
+  hipError_t e = hipEventRecord(lw->ev[0], st);
+  // 1. the map: sample, sorted sample, targets, initialisation, training
+  if (e == hipSuccess && !L.params) {
+    e = zs::launch_lsample(keys, m, (uint32_t)L.sample_stride, L.seed, lw->sample, st);
+    if (e == hipSuccess) {
+      zsort_config cs;
+      zsort_default_config(&cs);
+      Call sc{lw->sample, nullptr, 0, m, nullptr, 0, cs, 0, 0, false};
+      sc.slot = 1;
+      rc = run(sc, st, nullptr);
+      if (rc) return rc;
+    }
+    if (e == hipSuccess) e = zs::launch_lprep(lw->sample, m, lw->U, lw->Y, lw->res, st);
+    if (e == hipSuccess) e = zs::launch_linit(lw->sample, m, lw->par, st);
+    if (e == hipSuccess) e = zs::launch_ladam_reset(lw->adam, lw->res, st);
+    if (e == hipSuccess && L.steps > 0) {
+      // loss on minibatch 0 before and after training; the better parameters stay
+      e = hipMemcpyAsync(lw->par0, lw->par, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = zs::launch_ltrain(lw->U, lw->Y, m, nb, 0, lw->par, lw->adam, lw->part, lw->res, 0.0, 1,
+                              lw->gout, st);
+      for (int t = 0; t < L.steps && e == hipSuccess; ++t)
+        e = zs::launch_ltrain(lw->U, lw->Y, m, nb, (uint32_t)t, lw->par, lw->adam, lw->part,
+                              lw->res, L.lr, 0, nullptr, st);
+      if (e == hipSuccess)
+        e = zs::launch_ltrain(lw->U, lw->Y, m, nb, 0, lw->par, lw->adam, lw->part, lw->res, 0.0, 1,
+                              lw->gout1, st);
+      // the sample's largest cluster under each parameter set decides
+      if (e == hipSuccess) e = hipMemsetAsync(lw->hc, 0, 2 * zs::kKMax * 4, st);
+      if (e == hipSuccess) e = zs::launch_lhist_sample(lw->U, m, lw->par0, B, lw->hc, st);
+      if (e == hipSuccess)
+        e = zs::launch_lhist_sample(lw->U, m, lw->par, B, lw->hc + zs::kKMax, st);
+      if (e == hipSuccess)
+        e = zs::launch_lkeep(lw->par, lw->par0, lw->gout, lw->gout1, lw->hc, lw->hc + zs::kKMax, B,
+                             lw->res, st);
+    }
+  } else if (e == hipSuccess) {
+    e = hipMemcpyAsync(lw->par, L.params, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = zs::launch_ladam_reset(lw->adam, lw->res, st);
+    if (e == hipSuccess) e = zs::launch_lset_range(lw->res, L.smin, L.smax, st);
+  }
+  const bool direct = (L.flags & ZSORT_LEARNED_DIRECT) != 0;
+  if (e == hipSuccess && !direct) e = zs::launch_lthresh(lw->par, B, lw->res, lw->thr, st);
+  if (e == hipSuccess) e = hipEventRecord(lw->ev[1], st);
+  if (e != hipSuccess) return hip_fail(e);
+
+  // 2. the main workspace, sized for a first pass of B clusters
+  Shape s;
+  s.n = n;
+  s.pw = payload_bytes;
+  s.k = c.k;
+  s.cutoff = c.cutoff;
+  s.chunk = c.chunk;
+  s.tile = c.tile;
+  s.kfirst = B;
+  Workspace* w = nullptr;
+  rc = acquire(st, s, &w);
+  if (rc) return rc;
+  if (!pacing_ready(w)) return ZSORT_EHIP;
+  const Ws ws = make_ws(w, keys, pay, c, payload_bytes);
+  const Ws w0 = first_pass_ws(ws, lw, B, direct);
+  const int pw = payload_bytes;
+  if (L.flags & ZSORT_LEARNED_ZSCORE_DIAG) {
+    // the z-score map's histogram at the same cluster count (moments,
+    // statistics, histogram of the root; nothing moves)
+    Ws wd = w0;
+    std::memset(&wd.lm, 0, sizeof wd.lm);
+    e = zs::launch_reset(wd, st);
+    if (e == hipSuccess) e = zs::launch_init_single(wd, n, st);
+    for (int sid = zs::STAGE_MOMENTS; sid <= zs::STAGE_HIST && e == hipSuccess; ++sid)
+      e = stage(w, wd, 0, sid, grid_size(B, pw, wd.p.tile, sid), st);
+    if (e == hipSuccess) e = zs::launch_lmaxcount(wd.bstart, n, B, &lw->res->maxz, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // 3. learned first pass (hist writes the cluster ids, scatter moves key +
+  //    payload to the alternate buffer), then the order check
+  e = zs::launch_reset(ws, st);
+  if (e == hipSuccess) e = zs::launch_init_learned(ws, n, st);
+  if (e == hipSuccess) e = hipEventRecord(lw->ev[2], st);
+  if (e == hipSuccess) e = stage(w, w0, 0, zs::STAGE_HIST, grid_size(B, pw, w0.p.tile, zs::STAGE_HIST), st);
+  if (e == hipSuccess)
+    e = stage(w, w0, 0, zs::STAGE_SCATTER, grid_size(B, pw, w0.p.tile, zs::STAGE_SCATTER), st);
+  if (e == hipSuccess)
+    e = zs::launch_lcheck(ws.keys[1], ws.bstart, n, B, lw->bmin, lw->bmax, lw->res,
+                          std::max(1, g_cu_count) * 4, st);
+  if (e == hipSuccess && host_counts) e = zs::launch_lcounts(ws.bstart, n, B, lw->counts, st);
+  if (e == hipSuccess) e = hipEventRecord(lw->ev[3], st);
+  if (e == hipSuccess && host_counts)
+    e = hipMemcpyAsync(host_counts, lw->counts, (size_t)B * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lw->h_res, lw->res, sizeof(zs::LRes), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(lw->ev[4], st);
+  if (e == hipSuccess) e = hipEventSynchronize(lw->ev[4]);
+  if (e != hipSuccess) return hip_fail(e);
+  const zs::LRes r = *lw->h_res;
+  const double kp = 8.0 + pw;
+  double extra = 4.0 * (double)n + 8.0 * (double)n;  // cluster ids (write + read), check pass
+  if (r.fail) {
+    // 4a. the map broke the cluster order: the z-score path sorts the
+    //     caller's keys, which the first pass left untouched
+    e = enqueue(w, ws, call, st);
+    extra += (8.0 + 2.0 * kp) * (double)n;  // the discarded first pass
+  } else {
+    // 4b. local sort of the first pass's small clusters, then the z-score
+    //     levels 1, 2, ... on the large ones
+    e = stage(w, ws, 0, zs::STAGE_LOCAL, grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL), st);
+    if (e == hipSuccess)
+      e = stage(w, ws, 0, zs::STAGE_LOCAL_HARD, grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL_HARD), st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&w->h_nseg[1], &ws.ctl->nseg[1], sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         st);
+    if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[0], st);
+    if (e == hipSuccess) e = enqueue_levels(w, ws, call, st, 1);
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  w->calls++;
+  w->last_n = n;
+  w->last_pw = pw;
+  w->has_last = true;
+  w->last_extra_bytes = extra;
+  if (report) {
+    report->used_learned = r.fail ? 0 : 1;
+    report->fallback = r.fail ? 1 : 0;
+    report->thresholds = direct ? -1 : (int32_t)r.nt;
+    report->steps = L.params ? 0 : (int32_t)r.steps_done;
+    report->trained = (!L.params && L.steps > 0) ? (int32_t)r.trained : 0;
+    report->sample_max_init = r.smax_init;
+    report->sample_max_trained = r.smax_trained;
+    report->sample_keys = m;
+    report->max_cluster_learned = r.maxc;
+    report->max_cluster_zscore = r.maxz;
+    const double mean = (double)n / (double)B;
+    report->imbalance_learned = (double)r.maxc / mean;
+    report->imbalance_zscore = (L.flags & ZSORT_LEARNED_ZSCORE_DIAG) ? (double)r.maxz / mean : 0.0;
+    report->loss_first = r.loss_first;
+    report->loss_last = r.loss_last;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, lw->ev[0], lw->ev[1]) == hipSuccess) report->train_ms = ms;
+    if (hipEventElapsedTime(&ms, lw->ev[2], lw->ev[3]) == hipSuccess) report->first_pass_ms = ms;
+  }
+  return ZSORT_OK;
+}
+
+int zsort_learned_sample(const uint64_t* keys, size_t n, int32_t stride, uint64_t seed,
+                         uint64_t* out, void* stream) {
+  if (stride < 1 || n > 0x7FFFFFFFull || (n && (!keys || !out))) return ZSORT_EINVAL;
+  const uint64_t m = (uint64_t)n / (uint64_t)stride;
+  if (!m) return ZSORT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = zs::launch_lsample(keys, m, (uint32_t)stride, seed, out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? ZSORT_OK : hip_fail(e);
+}
+
+int zsort_mlp_forward(const zsort_mlp_params* params, const uint64_t* keys, size_t q, uint64_t smin,
+                      uint64_t smax, int32_t buckets, float* f_out, uint32_t* cluster_out,
+                      void* stream) {
+  if (!params || (q && !keys) || smin > smax || buckets < 1 || buckets > zs::kKMax ||
+      q > 0x7FFFFFFFull)
+    return ZSORT_EINVAL;
+  if (!q) return ZSORT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  LearnedWs* lw = nullptr;
+  int rc = lacquire(st, 0, 0, 0, &lw);
+  if (rc) return rc;
+  hipError_t e = zs::launch_lset_range(lw->res, smin, smax, st);
+  if (e == hipSuccess)
+    e = zs::launch_lforward((const zs::MlpP*)params, keys, q, lw->res, buckets, f_out, cluster_out,
+                            st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? ZSORT_OK : hip_fail(e);
+}
+
+int zsort_mlp_thresholds(const zsort_mlp_params* params, uint64_t smin, uint64_t smax, int32_t buckets,
+                         uint64_t* thr_out, int32_t* nt_out, void* stream) {
+  if (!params || !thr_out || !nt_out || smin > smax || buckets < 2 || buckets > zs::kKMax)
+    return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  LearnedWs* lw = nullptr;
+  int rc = lacquire(st, 0, 0, 0, &lw);
+  if (rc) return rc;
+  hipError_t e = zs::launch_lset_range(lw->res, smin, smax, st);
+  if (e == hipSuccess) e = zs::launch_lthresh((const zs::MlpP*)params, buckets, lw->res, thr_out, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lw->h_res, lw->res, sizeof(zs::LRes), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  *nt_out = (int32_t)lw->h_res->nt;
+  return ZSORT_OK;
+}
+
+int zsort_mlp_init(const uint64_t* sorted_sample, size_t m, zsort_mlp_params* params_out,
+                   void* stream) {
+  if (!sorted_sample || !params_out || m < 2 || m > 0x7FFFFFFFull) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = zs::launch_linit(sorted_sample, m, (zs::MlpP*)params_out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? ZSORT_OK : hip_fail(e);
+}
+
+int zsort_mlp_grad(const zsort_mlp_params* params, const uint64_t* sorted_sample, size_t m, double* grad_out,
+                   void* stream) {
+  if (!params || !sorted_sample || !grad_out || m < 2 || m > 0x7FFFFFFFull) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  LearnedWs* lw = nullptr;
+  int rc = lacquire(st, 0, m, zs::lpart_floats(m, 1), &lw);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(lw->par, params, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = zs::launch_lprep(sorted_sample, m, lw->U, lw->Y, lw->res, st);
+  if (e == hipSuccess) e = zs::launch_ladam_reset(lw->adam, lw->res, st);
+  if (e == hipSuccess)
+    e = zs::launch_ltrain(lw->U, lw->Y, m, 1, 0, lw->par, lw->adam, lw->part, lw->res, 0.0, 1,
+                          grad_out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? ZSORT_OK : hip_fail(e);
+}
+
+int zsort_mlp_train(zsort_mlp_params* params, const uint64_t* sorted_sample, size_t m, int32_t steps,
+                    int32_t batches, double lr, double* losses_out, void* stream) {
+  if (!params || !sorted_sample || m < 2 || m > 0x7FFFFFFFull || steps < 0 || batches < 1 ||
+      !(lr > 0.0))
+    return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  LearnedWs* lw = nullptr;
+  int rc = lacquire(st, 0, m, zs::lpart_floats(m, (uint32_t)batches), &lw);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(lw->par, params, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = zs::launch_lprep(sorted_sample, m, lw->U, lw->Y, lw->res, st);
+  if (e == hipSuccess) e = zs::launch_ladam_reset(lw->adam, lw->res, st);
+  for (int t = 0; t < steps && e == hipSuccess; ++t)
+    e = zs::launch_ltrain(lw->U, lw->Y, m, (uint32_t)batches, (uint32_t)t, lw->par, lw->adam,
+                          lw->part, lw->res, lr, 0, nullptr, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(params, lw->par, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lw->h_res, lw->res, sizeof(zs::LRes), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (losses_out) {
+    losses_out[0] = lw->h_res->loss_first;
+    losses_out[1] = lw->h_res->loss_last;
+  }
+  return ZSORT_OK;
 }
 
 int zsort_last_hip_error(void) { return g_last_hip; }

@@ -34,8 +34,9 @@ constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical 
 enum : int { STAGE_MOMENTS = 0, STAGE_FINALIZE = 1, STAGE_HIST = 2, STAGE_SCATTER = 3,
              STAGE_LOCAL = 4, STAGE_LOCAL_HARD = 5, NSTAGES = 6 };
 
-// segment kinds, as in the recursion records
-enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3 };
+// segment kinds, as in the recursion records; KIND_LMAP is the learned
+// partition map of the first pass (bucket ids precomputed by the hist pass)
+enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3, KIND_LMAP = 4 };
 // segment flags
 enum : uint32_t { F_RMAP = 1u, F_ROOT = 2u };
 // leaf-group flags
@@ -112,6 +113,45 @@ struct TraceRec {
   int64_t hist_off;
 };
 
+// monotone MLP 1 -> 32 -> 32 -> 1 of the learned partition map.  1153
+// parameters, indexed (gradients, optimizer state) in the order W1[32],
+// b1[32], W2[32][32] (row = output unit), b2[32], W3[32], b3.  The first
+// layer is binary64: a ramp must be placed to a fraction of its width, and
+// a narrow, heavy component of the key distribution can span less than
+// binary32's resolution of the normalised range.
+constexpr int kH = 32;
+constexpr int kNP = 1153;
+constexpr int kW1 = 0, kB1 = 32, kW2 = 64, kB2 = 1088, kW3 = 1120, kB3 = 1152;
+struct MlpP {
+  double w1[kH], b1[kH];
+  float w2[kH * kH], b2[kH], w3[kH], b3;
+};
+
+// device-side results of the learned map's set-up and check
+struct LRes {
+  uint64_t smin, smax;   // normalisation range: the sample's minimum and maximum
+  uint32_t nt;           // number of thresholds
+  uint32_t fail;         // 1: some cluster's maximum exceeds a later cluster's minimum
+  uint64_t maxc;         // largest first-pass cluster of the learned map
+  uint64_t maxz;         // largest cluster of the z-score map at the same count (diagnostic)
+  uint32_t ticket;       // last-workgroup ticket of a training step
+  uint32_t steps_done;
+  double loss_first, loss_last;  // loss on minibatch 0 before training / of the kept parameters
+  uint32_t trained;              // 1: the trained parameters were kept (not the initial ones)
+  uint32_t pad;
+  uint32_t smax_init, smax_trained;  // largest cluster of the sample under each parameter set
+};
+
+// learned map of the first pass
+struct LMap {
+  const uint64_t* thr;   // thresholds t_1..t_nt: t_b is the least key whose cluster is >= b
+  const MlpP* par;       // parameters (direct per-key inference only)
+  uint16_t* ids;         // cluster id of each key, written by hist, read by scatter
+  const LRes* res;       // normalisation range and threshold count
+  int32_t direct;        // 1: evaluate the MLP per key instead of searching the thresholds
+  int32_t pad;
+};
+
 struct Params {
   int32_t k;             // clusters per pass
   int32_t lb;            // floor(log2 k), range-map bits per pass
@@ -140,6 +180,7 @@ struct Ws {
   uint32_t trace_cap, trace_hist_cap;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap;
   Params p;
+  LMap lm;
 };
 
 }  // namespace zs

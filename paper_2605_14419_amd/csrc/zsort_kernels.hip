@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include "zsort_internal.h"
+#include "zsort_mlp.h"
 
 namespace zs {
 
@@ -290,8 +291,8 @@ __device__ __forceinline__ void for_each_key(const uint64_t* __restrict__ x, uin
   const uint64_t a0 = beg + ((beg + mis) & 1u);
   const uint64_t a1 = end - ((end + mis) & 1u);
   const int t = threadIdx.x;
-  if (t == 0 && beg < a0 && beg < end) f(x[beg]);
-  if (t == 1 && a1 >= a0 && a1 < end) f(x[a1]);
+  if (t == 0 && beg < a0 && beg < end) f(beg, x[beg]);
+  if (t == 1 && a1 >= a0 && a1 < end) f(a1, x[a1]);
   if (a1 <= a0) return;
   const ulonglong2* __restrict__ xp = reinterpret_cast<const ulonglong2*>(x + a0);
   const uint64_t np = (a1 - a0) >> 1;
@@ -305,7 +306,7 @@ __device__ __forceinline__ void for_each_key(const uint64_t* __restrict__ x, uin
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const uint64_t q = p + (uint64_t)u * kBlock;
-      if (q < np) { f(v[u].x); f(v[u].y); }
+      if (q < np) { f(a0 + 2 * q, v[u].x); f(a0 + 2 * q + 1, v[u].y); }
     }
   }
 }
@@ -420,6 +421,26 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
     ws.work[0][i] = (uint64_t)i;  // segment 0, chunk i
+}
+
+// one array [0, n), n > cutoff, whose first pass uses the learned map
+__global__ void k_init_learned(Ws ws, uint64_t n) {
+  Ctl* c = ws.ctl;
+  const uint64_t ch = (uint64_t)ws.p.chunk;
+  const uint32_t nch = (uint32_t)((n + ch - 1) / ch);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    make_root_seg(ws, 0, 0, n, 0, nch, 0);
+    Seg& s = ws.segs[0][0];
+    s.flags = 0;
+    s.kind = KIND_LMAP;
+    s.o = 0;
+    s.M = ~0ull;
+    c->nseg[0] = 1;
+    c->nwork[0] = nch;
+    c->nstatus[0] = nch > 1 ? nch : 0;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
+    ws.work[0][i] = (uint64_t)i;
 }
 
 // independent arrays [off[i], off[i+1]); offsets were validated by k_check_offsets
@@ -583,7 +604,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, b0 = 0, b1 = 0;
     uint64_t mn = ~0ull, mx = 0;
-    for_each_key<4>(x, beg, end, [&](uint64_t v) {
+    for_each_key<4>(x, beg, end, [&](uint64_t, uint64_t v) {
       const uint32_t xl = (uint32_t)v, xh = (uint32_t)(v >> 32);
       const uint64_t ll = (uint64_t)xl * xl, lh = (uint64_t)xl * xh, hh = (uint64_t)xh * xh;
       a0 += (uint32_t)ll; a1 += ll >> 32;
@@ -665,7 +686,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Ws ws, int L) {
 // segment, and in the last chunk the exclusive scan + classification
 // ---------------------------------------------------------------------------
 template <int KMAX>
-struct HistSmem {
+struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned thresholds)
   uint32_t h[KMAX];       // histogram, later totals
   uint32_t bst[KMAX];     // exclusive starts
   uint32_t t0[KMAX];      // scratch arrays for classification
@@ -721,6 +742,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
                     sm.base_status + nstat <= ws.status_cap;
   const double scale = (double)k / 4.0;
   const bool parent_r = sg.kind == KIND_RMAP;
+  const bool parent_l = sg.kind == KIND_LMAP;  // children take their exact mean
   if (fits) {
     for (int b = t; b < k; b += kBlock) {
       const uint32_t n = sm.h[b];
@@ -732,7 +754,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       cs.count = n;
       cs.o_parent = sg.o;
       double e = 0.0;
-      if (!crm) {  // estimated mean of cluster b, parent's frame
+      if (!crm && !parent_l) {  // estimated mean of cluster b, parent's frame
         double q = ((double)b + 0.5) / scale;
         q = q - sg.zmin;
         q = q * sg.sigma;
@@ -740,7 +762,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       }
       cs.e = e;
       cs.depth = L + 1;
-      cs.flags = crm ? F_RMAP : 0u;
+      cs.flags = crm ? F_RMAP : (parent_l ? F_ROOT : 0u);
       cs.nchunks = (uint32_t)((n + ch - 1) / ch);
       cs.first_work = sm.base_work + sm.t1[b];
       cs.status_base = sm.base_status + sm.t2[b];
@@ -863,7 +885,10 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   __syncthreads();
 }
 
-template <int KMAX>
+// LM: the learned first pass (every segment has KIND_LMAP); a separate
+// instance so that the per-key MLP of its direct mode does not raise the
+// register count of the plain histogram
+template <int KMAX, bool LM>
 __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   __shared__ HistSmem<KMAX> sm;
   Ctl* c = ws.ctl;
@@ -891,7 +916,27 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     for (int b = t; b < k; b += kBlock) sm.h[b] = 0;
     __syncthreads();
-    for_each_key<4>(x, beg, end, [&](uint64_t v) { atomicAdd(&sm.h[bucket_of(v, mp)], 1u); });
+    if constexpr (LM) {
+      // learned map: cluster = number of thresholds <= key (binary search in
+      // LDS), or the MLP evaluated per key; the ids go to the scatter pass
+      const uint32_t nt = min(ws.lm.res->nt, (uint32_t)(k - 1));
+      uint64_t* thr = reinterpret_cast<uint64_t*>(sm.t0);  // t0, t1: KMAX words
+      if (!ws.lm.direct)
+        for (uint32_t q = t; q < nt; q += kBlock) thr[q] = ws.lm.thr[q];
+      __syncthreads();
+      const uint32_t top = top_pow2(nt);
+      const uint64_t smin = ws.lm.res->smin, smax = ws.lm.res->smax;
+      uint16_t* __restrict__ ids = ws.lm.ids;
+      for_each_key<4>(x, beg, end, [&](uint64_t i, uint64_t v) {
+        const uint32_t b = ws.lm.direct ? mlp_cluster(*ws.lm.par, v, smin, smax, k)
+                                        : thr_cluster(thr, nt, top, v);
+        atomicAdd(&sm.h[b], 1u);
+        ids[i] = (uint16_t)b;
+      });
+    } else {
+      for_each_key<4>(x, beg, end,
+                      [&](uint64_t, uint64_t v) { atomicAdd(&sm.h[bucket_of(v, mp)], 1u); });
+    }
     __syncthreads();
     const uint32_t nch = sg.nchunks;
     if (nch > 1) {
@@ -979,6 +1024,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
     const Seg& sg = ws.segs[S][si];
     if (sg.kind == KIND_IDENT) continue;
     const MapP mp = map_of(sg, k);
+    const bool lmap = sg.kind == KIND_LMAP;
     const uint64_t beg = sg.start + (uint64_t)ci * ch;
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     const uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
@@ -1001,12 +1047,13 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         const bool valid = i < tn;
         key[r] = valid ? xin[tb + i] : 0ull;
         pay[r] = valid ? pay_load<PW>(pin, tb + i) : (P)0;
+        bk[r] = (lmap && valid) ? (uint32_t)ws.lm.ids[tb + i] : 0u;  // learned map: ids of hist
       }
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
         const bool valid = i < tn;
-        const uint32_t b = valid ? bucket_of(key[r], mp) : 0u;
+        const uint32_t b = valid ? (lmap ? bk[r] : bucket_of(key[r], mp)) : 0u;
         const uint64_t act = __ballot(valid);
         const uint64_t m = match_digit<KBITS>(b, act);
         const uint32_t before = below(m);
@@ -1646,7 +1693,7 @@ static const void* stage_fn(int stage) {
   switch (stage) {
     case STAGE_MOMENTS: return (const void*)k_moments;
     case STAGE_FINALIZE: return (const void*)k_finalize;
-    case STAGE_HIST: return (const void*)k_hist<KMAX>;
+    case STAGE_HIST: return (const void*)k_hist<KMAX, false>;
     case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS>;
     case STAGE_LOCAL: return (const void*)k_local<PW>;
     default: return (const void*)k_local_hard<PW>;
@@ -1663,7 +1710,10 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_HIST:
-      hipLaunchKernelGGL((k_hist<KMAX>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      if (ws.lm.ids)
+        hipLaunchKernelGGL((k_hist<KMAX, true>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      else
+        hipLaunchKernelGGL((k_hist<KMAX, false>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_SCATTER:
       hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(grid), dim3(kBlock), 0, st, ws,
@@ -1690,6 +1740,11 @@ hipError_t launch_reset(const Ws& ws, hipStream_t st) {
 
 hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_init_single, dim3(64), dim3(kBlock), 0, st, ws, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_learned(const Ws& ws, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_learned, dim3(64), dim3(kBlock), 0, st, ws, n);
   return hipGetLastError();
 }
 

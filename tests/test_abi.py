@@ -26,6 +26,26 @@ def test_header_declares_expected_entry_points():
     assert set(names) == set(zs.EXPORTED)
 
 
+def declared_arity():
+    src = open(os.path.join(ROOT, "include", "zsort.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(zsort_\w+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    L = zs.lib()
+    ar = declared_arity()
+    assert set(ar) == set(declared_functions())
+    for name, n in ar.items():
+        at = getattr(L, name).argtypes
+        if at is not None:
+            assert len(at) == n, (name, len(at), n)
+
+
 def test_library_exports_every_declared_symbol():
     L = zs.lib()
     for name in declared_functions():

@@ -77,24 +77,47 @@ def test_tiny_network_closed_form():
     assert oracle.mlp_bucket(p, U64, 0, U64, 4096) == 3072
 
 
-def test_quantile_init_interpolates_the_sample_cdf():
-    keys, _ = synth.make("gmm", 50_000)
+def _pieces(p):
+    """ramps of an initialised map: (start u, end u, height) per used unit"""
+    out = []
+    for r in range(32):
+        w, b, h = p[oracle.W1 + r], p[oracle.B1 + r], p[oracle.W3 + r]
+        if h == 0:
+            continue
+        out.append((-b / w, (1 - b) / w, h))
+    return out
+
+
+@pytest.mark.parametrize("wl", ["gmm", "uniform", "dup_heavy"])
+def test_init_interpolates_the_sample_cdf(wl):
+    """f at the first and the last key of each piece equals the sample's CDF
+    there (share of the sample before the piece, through the piece), up to
+    the rounding of the heights to binary32, of W1/b1 and of the
+    pre-activations; pieces tile the sample; the mixture's gaps are cut"""
+    keys, _ = synth.make(wl, 50_000)
     s = np.sort(keys)
     smin, smax = int(s[0]), int(s[-1])
     p = oracle.mlp_init(s, smin, smax)
     m = s.size
-    for i in range(0, 33):
-        idx = int(i * (m - 1) / 32)
-        q = oracle.mlp_norm(int(s[idx]), smin, smax)
-        f = oracle.mlp_forward(p, q)
-        # f(q_i) = i/32 up to the float32 rounding of W1, b1 and of each
-        # first-layer pre-activation (propagated through W2 = I and W3 = 1/32)
-        # plus the 32 float32 additions of the output sum
-        w1 = p[oracle.W1:oracle.W1 + 32].astype(np.float64)
-        b1 = p[oracle.B1:oracle.B1 + 32].astype(np.float64)
-        tol = ((np.abs(w1) * q + np.abs(b1) + 1).sum() / 32 + 32) * 2.0**-23
-        assert abs(f - i / 32) <= tol, (i, f, tol)
-    assert np.all(p[oracle.W1:oracle.W1 + 32] > 0)
+    heights = p[oracle.W3:oracle.W3 + 32]
+    assert abs(heights.sum() - 1.0) < 32 * 2.0**-24
+    assert np.all(p[oracle.W1:oracle.W1 + 32] >= 0)
+    cum = 0.0
+    starts = []
+    for lo, hi, h in _pieces(p):
+        # lo, hi: the piece's first and last normalised key; f there
+        f_lo = oracle.mlp_forward(p, lo)
+        f_hi = oracle.mlp_forward(p, hi)
+        tol = 64 * 2.0**-24
+        assert abs(f_lo - cum) <= tol, (f_lo, cum)
+        cum += h
+        if hi > lo:
+            assert abs(f_hi - cum) <= tol, (f_hi, cum)
+        starts.append(lo)
+    assert abs(cum - 1.0) < 32 * 2.0**-24
+    assert starts == sorted(starts)
+    if wl == "gmm":  # four separated components: the three gaps are cut
+        assert len(_pieces(p)) >= 28 + 3
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -130,3 +153,41 @@ def test_mid_rank_targets():
     y = oracle.mlp_targets(s)
     # (#{< x} + #{<= x}) / (2m): the middle of each key's run of ranks
     assert y.tolist() == [0.1, 0.5, 0.5, 0.5, 0.9]
+
+
+def test_adam_first_step_is_lr_times_sign_and_keeps_weights_nonnegative():
+    """Adam's first bias-corrected step is lr * g / (|g| + eps), i.e. lr * sign(g)
+    for |g| >> eps; projected weights never go negative."""
+    rng = np.random.default_rng(11)
+    p = random_params(4)
+    p[oracle.W3:oracle.W3 + 4] = 0.0          # on the boundary of the projection
+    u = rng.uniform(0, 1, 64)
+    y = np.sort(rng.uniform(0, 1, 64))
+    _, g = oracle.mlp_loss_grad(p, u, y)
+    lr = 2.0**-12
+    p1, lf, ll = oracle.mlp_train(p, u, y, steps=1, batches=1, lr=lr)
+    assert lf == ll
+    big = np.abs(g) > 1e-6
+    want = p.astype(np.float64) - lr * np.sign(g)
+    wmask = np.zeros(oracle.MLP_NP, dtype=bool)
+    wmask[oracle.W1:oracle.B1] = wmask[oracle.W2:oracle.B2] = wmask[oracle.W3:oracle.B3] = True
+    want[wmask] = np.maximum(want[wmask], 0.0)
+    tol = np.abs(want) * 2.0**-23 + lr * 1e-2
+    assert np.all(np.abs(p1[big] - want[big]) <= tol[big])
+    assert np.all(p1[wmask] >= 0)
+
+
+def test_training_reduces_the_loss_on_a_mixture_sample():
+    keys, _ = synth.make("gmm", 100_000)
+    s = np.sort(keys[::50])
+    smin, smax = int(s[0]), int(s[-1])
+    p = oracle.mlp_init(s, smin, smax)
+    u = np.array([oracle.mlp_norm(int(x), smin, smax) for x in s])
+    y = oracle.mlp_targets(s)
+    l0, _ = oracle.mlp_loss_grad(p, u, y)
+    p2, _, _ = oracle.mlp_train(p, u, y, steps=48, batches=8, lr=1e-3)
+    l1, _ = oracle.mlp_loss_grad(p2, u, y)
+    assert l1 < 0.8 * l0
+    # still monotone after training (projection)
+    f = np.array([oracle.mlp_forward(p2, float(v)) for v in np.linspace(0, 1, 5001)])
+    assert np.all(np.diff(f) >= 0)
