@@ -39,7 +39,7 @@ EXTRAS = {
     "gmm_zscore": dict(workload="gmm", n=10**8, payload_bytes=4,
                        desc="plain z-score path on the 4-component mixture, 1e8 keys, u32 index"),
 }
-DEFAULT_CFG = dict(k=1024, cutoff=2048, max_zlevels=8, chunk=16384)
+DEFAULT_CFG = dict(k=1024, cutoff=2048, max_zlevels=8, chunk=16384, tile=2048)
 
 
 def log(*a):
@@ -195,7 +195,68 @@ def run_batched(steps, warmup, dev, nseg=4096):
             "speedup_vs_loop": round(l_ms / g_ms, 2)}
 
 
-def roofline(kt, stats, pw, steps, traffic_file):
+def run_learned(steps, warmup, dev, n=10**8):
+    """Learned first-pass map on the 4-component mixture (narrow heavy
+    component mid-range), against the z-score map: whole-sort time with the
+    model fitted inside every call, time with a fitted model reused, and the
+    first-pass imbalance (largest cluster / mean) of both maps at 4096
+    clusters."""
+    import synth
+    import torch
+    import paper_2605_14419_amd as zs
+
+    keys, pay = synth.make("gmm", n, payload_bytes=4)
+    base_k, base_p = to_device(keys, pay, dev)
+    del keys, pay
+    cfg = zs.zsort_autotune(base_k, base_p)
+    par = torch.empty(zs.MLP_PARAMS_BYTES, dtype=torch.uint8, device=dev)
+    k, p = base_k.clone(), base_p.clone()
+    diag = zs.zsort_stable_learned(k, p, cfg, dict(flags=zs.ZSORT_LEARNED_ZSCORE_DIAG),
+                                   params_out=par)
+    verify_on_device(base_k, k, p)
+    del k, p
+    reuse = dict(params=par, smin=diag["smin_out"], smax=diag["smax_out"])
+
+    def timed(lcfg):
+        ins = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
+        for _ in range(warmup):
+            zs.zsort_stable_learned(base_k.clone(), base_p.clone(), cfg, lcfg)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        reps = [zs.zsort_stable_learned(ins[i][0], ins[i][1], cfg, lcfg) for i in range(steps)]
+        ev1.record()
+        torch.cuda.synchronize()
+        verify_on_device(base_k, ins[-1][0], ins[-1][1])
+        del ins
+        torch.cuda.empty_cache()
+        return ev0.elapsed_time(ev1) / steps, reps
+
+    ms_fit, reps = timed(None)
+    ms_reuse, reps2 = timed(reuse)
+    st = zs.zsort_get_last_stats()
+    log(f"[bench] learned: {ms_fit:.3f} ms/step fitted per call, {ms_reuse:.3f} reused; imbalance "
+        f"{diag['imbalance_learned']:.2f} vs z-score {diag['imbalance_zscore']:.1f}")
+    return {"workload": f"{n} u64 keys, 4-component mixture (narrow heavy component mid-range), "
+                        "u32 index payload, 4096 first-pass clusters",
+            "config": cfg,
+            "ms_per_step": round(ms_fit, 4), "gkeys_per_s": round(n / ms_fit / 1e6, 3),
+            "ms_per_step_model_reused": round(ms_reuse, 4),
+            "gkeys_per_s_model_reused": round(n / ms_reuse / 1e6, 3),
+            "fit_ms": round(sum(r["train_ms"] for r in reps) / len(reps), 4),
+            "first_pass_ms": round(sum(r["first_pass_ms"] for r in reps2) / len(reps2), 4),
+            "imbalance_learned": round(diag["imbalance_learned"], 3),
+            "imbalance_zscore": round(diag["imbalance_zscore"], 3),
+            "used_learned": sum(r["used_learned"] for r in reps + reps2),
+            "fallbacks": sum(r["fallback"] for r in reps + reps2),
+            "trained_kept": sum(r["trained"] for r in reps),
+            "sample_max_cluster_init_vs_trained": [reps[0]["sample_max_init"],
+                                                   reps[0]["sample_max_trained"]],
+            "levels": st["levels"], "calls": len(reps) + len(reps2)}
+
+
+def roofline(kt, stats, pw, steps, traffic_file, cfg):
     per_step = stage_bytes(stats, pw)
     dom = max(STAGES, key=lambda s: kt[s][0])
     tot_ms, launches = kt[dom]
@@ -206,12 +267,116 @@ def roofline(kt, stats, pw, steps, traffic_file):
     if os.path.exists(traffic_file):
         with open(traffic_file) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_source_hash() and tr.get("stage") == dom:
+        same_cfg = all(tr.get("config", {}).get(x) == cfg.get(x) for x in ("k", "tile", "chunk"))
+        if tr.get("kernel_hash") == kernel_source_hash() and tr.get("stage") == dom and same_cfg:
             traffic = tr.get("bytes_per_launch")
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
             "launches": launches}
+
+
+STAGE_OF_KERNEL = (("k_moments", "moments"), ("k_finalize", "finalize"), ("k_hist", "hist"),
+                   ("k_scatter", "scatter"), ("k_local_hard", "local_hard"), ("k_local", "local"))
+
+
+def _stage_of(name):
+    for pat, st in STAGE_OF_KERNEL:
+        if pat + "<" in name or pat + "(" in name:
+            return st
+    return None
+
+
+def _csv(dirname, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(dirname, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {dirname}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profiles(d, workload, cfg):
+    """Turns the csv output of three rocprofv3 runs of this script (kernel
+    trace + stats; FETCH_SIZE; WRITE_SIZE, both with --copy-probe) into the
+    text summaries kept beside the code.  `d` holds kt/, fetch/, write/ and
+    commands.txt (one "kt: ...", "fetch: ...", "write: ..." line each)."""
+    cmds = {}
+    with open(os.path.join(d, "commands.txt")) as fh:
+        for ln in fh:
+            if ":" in ln:
+                a, b = ln.split(":", 1)
+                cmds[a.strip()] = b.strip()
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    # kernel time
+    rows = _csv(os.path.join(d, "kt"), "_kernel_stats.csv")
+    lines = [f"# Kernel time, {workload}", "", "Command (from the repository root):", "",
+             "    " + cmds.get("kt", "?"), "",
+             "| kernel | stage | calls | total ms | avg us | % |", "|---|---|---|---|---|---|"]
+    per_stage = {}
+    for r in rows:
+        st = _stage_of(r["Name"]) or "-"
+        nm = r["Name"].replace("void ", "").replace("(zs::Ws, int)", "").replace("|", "/")
+        lines.append(f"| `{nm[:70]}` | {st} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {r['Percentage']} |")
+        if st != "-":
+            a = per_stage.setdefault(st, [0, 0])
+            a[0] += int(r["TotalDurationNs"])
+            a[1] += int(r["Calls"])
+    lines += ["", "Per stage (all template instances):", "", "| stage | calls | total ms | avg us |",
+              "|---|---|---|---|"]
+    for st, (ns, c) in sorted(per_stage.items(), key=lambda x: -x[1][0]):
+        lines.append(f"| {st} | {c} | {ns / 1e6:.3f} | {ns / c / 1e3:.1f} |")
+    with open(os.path.join(out_dir, f"kernels_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # HBM traffic, calibrated on the copy probe (1 GiB read + 1 GiB written per copy)
+    def counter(sub, cname):
+        per = {}
+        probe = []
+        for r in _csv(os.path.join(d, sub), "_counter_collection.csv"):
+            if r["Counter_Name"] != cname:
+                continue
+            kib = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"] and len(probe) < 3:
+                probe.append(kib)   # the probe's three copies run before anything else
+            st = _stage_of(r["Kernel_Name"])
+            if st:
+                a = per.setdefault(st, [0.0, 0])
+                a[0] += kib
+                a[1] += 1
+        return per, probe
+    fetch, fprobe = counter("fetch", "FETCH_SIZE")
+    write, wprobe = counter("write", "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    ff = gib_kib / (sum(fprobe) / len(fprobe))
+    wf = gib_kib / (sum(wprobe) / len(wprobe))
+    lines = [f"# HBM traffic per launch, {workload}", "",
+             "Commands (from the repository root):", "", "    " + cmds.get("fetch", "?"),
+             "    " + cmds.get("write", "?"), "",
+             f"Copy probe (1 GiB read, 1 GiB written per copy): FETCH_SIZE reads "
+             f"{sum(fprobe) / len(fprobe) / 1024:.1f} MiB -> factor {ff:.3f}; WRITE_SIZE reads "
+             f"{sum(wprobe) / len(wprobe) / 1024:.1f} MiB -> factor {wf:.3f}.", "",
+             "| stage | launches | fetch MB/launch (scaled) | write MB/launch (scaled) | total MB/launch |",
+             "|---|---|---|---|---|"]
+    traffic = {}
+    for st in STAGES:
+        if st not in fetch or st not in write:
+            continue
+        fb = fetch[st][0] / fetch[st][1] * 1024 * ff
+        wb = write[st][0] / write[st][1] * 1024 * wf
+        traffic[st] = fb + wb
+        lines.append(f"| {st} | {fetch[st][1]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+    with open(os.path.join(out_dir, f"traffic_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    dom = max(per_stage, key=lambda s: per_stage[s][0])
+    with open(os.path.join(out_dir, f"traffic_{workload}.json"), "w") as fh:
+        json.dump({"kernel_hash": kernel_source_hash(), "stage": dom, "config": cfg,
+                   "bytes_per_launch": round(traffic.get(dom, 0.0)),
+                   "per_stage_bytes_per_launch": {k: round(v) for k, v in traffic.items()},
+                   "fetch_factor": ff, "write_factor": wf}, fh, indent=1)
+    print(f"wrote kernels_{workload}.md, traffic_{workload}.md/.json (dominant {dom})")
 
 
 def cpu_baseline(keys, cfg, budget_s):
@@ -237,14 +402,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["batched"]),
+    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["learned", "batched"]),
                     help="comma list, or 'none'")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=PRIMARY["n"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--config", default=None,
+                    help="fixed configuration for the primary workload instead of the "
+                         "autotuner's, e.g. k=256,cutoff=2048,chunk=32768,tile=4096")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 csv output and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        if not args.config:
+            raise SystemExit("--summarize-profiles needs the --config the profiled runs used")
+        pc = dict(DEFAULT_CFG)
+        for kv in args.config.split(","):
+            a, b = kv.split("=")
+            pc[a.strip()] = int(b)
+        summarize_profiles(args.summarize_profiles, PRIMARY["workload"], pc)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
@@ -266,13 +445,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies")
-    keys, ms, stats, kt, cfg = run_workload(spec, args.steps, args.warmup, None, dev)
+    fixed = None
+    if args.config:
+        fixed = dict(DEFAULT_CFG)
+        for kv in args.config.split(","):
+            a, b = kv.split("=")
+            fixed[a.strip()] = int(b)
+    keys, ms, stats, kt, cfg = run_workload(spec, args.steps, args.warmup, fixed, dev)
     pw = spec["payload_bytes"]
     n = spec["n"]
     value = n / (ms * 1e-3) / 1e9
     model = stats["model_bytes"]
     rl = roofline(kt, stats, pw, args.steps,
-                  os.path.join(ROOT, "profiles", f"traffic_{spec['workload']}.json"))
+                  os.path.join(ROOT, "profiles", f"traffic_{spec['workload']}.json"), cfg)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GKeys/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -291,6 +476,14 @@ def main():
         for name in args.extras.split(","):
             if name == "batched":
                 extras[name] = run_batched(max(3, args.steps // 2), 1, dev)
+                continue
+            if name == "learned":
+                extras[name] = run_learned(max(3, args.steps // 2), 1, dev)
+                if "gmm_zscore" in extras:
+                    z = extras["gmm_zscore"]["ms_per_step"]
+                    extras[name]["zscore_ms_per_step_same_keys"] = z
+                    extras[name]["speedup_vs_zscore_model_reused"] = round(
+                        z / extras[name]["ms_per_step_model_reused"], 3)
                 continue
             es = EXTRAS[name]
             ek, ems, est, ekt, ecfg = run_workload(es, max(3, args.steps // 2), 1, None, dev)

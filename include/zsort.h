@@ -268,7 +268,10 @@ int zsort_profile_end(void* stream, zsort_kernel_times* out /* host */);
  * (cluster = number of thresholds <= key, found by binary search in LDS;
  * or, with ZSORT_LEARNED_DIRECT, the MLP evaluated per key); (3) checks on
  * the device that every non-empty cluster's maximum is <= the minimum of
- * every later cluster; (4) if the check passes, finishes with the z-score
+ * every later cluster -- with thresholds by checking that they are sorted
+ * (which implies it), with per-key inference (or ZSORT_LEARNED_VERIFY) by
+ * taking every cluster's minimum and maximum from the first pass's output;
+ * (4) if the check passes, finishes with the z-score
  * recursion (children take their exact mean); otherwise sorts the caller's
  * keys, which the first pass left untouched, with the plain z-score path.
  * The output is the same stable sort in every case.
@@ -287,10 +290,11 @@ typedef struct zsort_mlp_params {
 } zsort_mlp_params;
 #define ZSORT_LEARNED_DIRECT 1u       /* per-key MLP inference in the first pass */
 #define ZSORT_LEARNED_ZSCORE_DIAG 2u  /* also count the z-score map's clusters at B */
+#define ZSORT_LEARNED_VERIFY 4u       /* scan the first pass's output in the order check */
 typedef struct zsort_learned_config {
   int32_t buckets;        /* B: clusters of the first pass, 16..4096; default 4096 */
   int32_t sample_stride;  /* one key per stride is sampled; default 100 (1 %) */
-  int32_t steps;          /* Adam steps, 0 = initialisation only; default 32 */
+  int32_t steps;          /* Adam steps, 0 = initialisation only; default 16 */
   int32_t batches;        /* step t uses samples i with i mod batches == t mod batches; default 64 */
   double lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8); default 1e-4 */
   uint64_t seed;          /* sample offsets */
@@ -321,6 +325,10 @@ typedef struct zsort_learned_report {
   double first_pass_ms;          /* device time: learned first pass and order check */
   uint32_t* counts;              /* HOST, B words, or NULL: cluster sizes of the learned first
                                     pass (set by the caller; left in place) */
+  zsort_mlp_params* params_out;  /* DEVICE or NULL (set by the caller; left in place): receives
+                                    the parameters the first pass used, for reuse through
+                                    zsort_learned_config.params with smin_out / smax_out */
+  uint64_t smin_out, smax_out;   /* their normalisation range */
 } zsort_learned_report;
 
 int zsort_default_learned_config(zsort_learned_config* lcfg);

@@ -33,6 +33,7 @@ ZSORT_MLP_PARAMS = 1153
 MLP_PARAMS_BYTES = 4872   # sizeof(zsort_mlp_params): 64 binary64, 1089 binary32, padding
 ZSORT_LEARNED_DIRECT = 1
 ZSORT_LEARNED_ZSCORE_DIAG = 2
+ZSORT_LEARNED_VERIFY = 4
 STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
 
 
@@ -73,7 +74,9 @@ class ZsortLearnedReport(ctypes.Structure):
                 ("max_cluster_zscore", ctypes.c_uint64), ("imbalance_learned", ctypes.c_double),
                 ("imbalance_zscore", ctypes.c_double), ("loss_first", ctypes.c_double),
                 ("loss_last", ctypes.c_double), ("train_ms", ctypes.c_double),
-                ("first_pass_ms", ctypes.c_double), ("counts", ctypes.c_void_p)]
+                ("first_pass_ms", ctypes.c_double), ("counts", ctypes.c_void_p),
+                ("params_out", ctypes.c_void_p), ("smin_out", ctypes.c_uint64),
+                ("smax_out", ctypes.c_uint64)]
 
 
 class ZsortKernelTimes(ctypes.Structure):
@@ -340,9 +343,12 @@ def zsort_default_learned_config(**overrides) -> ZsortLearnedConfig:
     return c
 
 
-def zsort_stable_learned(keys, payload=None, cfg=None, lcfg=None, counts=False, stream=None):
+def zsort_stable_learned(keys, payload=None, cfg=None, lcfg=None, counts=False, params_out=None,
+                         stream=None):
     """Sort with the learned first-pass map; returns the report as a dict
-    (with the first-pass cluster sizes under "counts" when counts=True)."""
+    (with the first-pass cluster sizes under "counts" when counts=True; the
+    parameters used are copied into params_out, a device uint8 tensor of
+    MLP_PARAMS_BYTES, when given)."""
     p, pw = _pay(payload, keys.numel())
     if isinstance(lcfg, dict):
         lcfg = zsort_default_learned_config(**lcfg)
@@ -351,11 +357,13 @@ def zsort_stable_learned(keys, payload=None, cfg=None, lcfg=None, counts=False, 
     cbuf = np.zeros(buckets, dtype=np.uint32) if counts else None
     if cbuf is not None:
         rep.counts = cbuf.ctypes.data
+    if params_out is not None:
+        rep.params_out = _pptr(params_out).value
     _check("zsort_stable_learned", lib().zsort_stable_learned(
         _keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg),
         None if lcfg is None else ctypes.byref(lcfg), ctypes.byref(rep), _stream(stream)))
     out = {f: getattr(rep, f) for f, _ in ZsortLearnedReport._fields_
-           if f not in ("counts", "reserved")}
+           if f not in ("counts", "reserved", "params_out")}
     if cbuf is not None:
         out["counts"] = cbuf
     return out

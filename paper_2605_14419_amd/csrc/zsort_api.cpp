@@ -30,7 +30,8 @@ hipError_t launch_lsample(const uint64_t* x, uint64_t m, uint32_t stride, uint64
 hipError_t launch_lprep(const uint64_t* s, uint64_t m, double* U, float* Y, LRes* res,
                         hipStream_t st);
 hipError_t launch_lset_range(LRes* res, uint64_t smin, uint64_t smax, hipStream_t st);
-hipError_t launch_linit(const uint64_t* s, uint64_t m, MlpP* par, hipStream_t st);
+hipError_t launch_linit(const uint64_t* s, uint64_t m, MlpP* par, LRes* res, hipStream_t st);
+hipError_t launch_lthr_check(const uint64_t* thr, LRes* res, hipStream_t st);
 hipError_t launch_ladam_reset(double* adam, LRes* res, hipStream_t st);
 size_t lpart_floats(uint64_t m, uint32_t nb);
 hipError_t launch_ltrain(const double* U, const float* Y, uint64_t m, uint32_t nb, uint32_t step,
@@ -656,7 +657,8 @@ int check_lcfg(const zsort_learned_config* L) {
     return ZSORT_EINVAL;
   if (!(L->lr > 0.0) || !(L->lr < 1e6)) return ZSORT_EINVAL;
   if (L->params && L->smin > L->smax) return ZSORT_EINVAL;
-  if (L->flags & ~(uint32_t)(ZSORT_LEARNED_DIRECT | ZSORT_LEARNED_ZSCORE_DIAG)) return ZSORT_EINVAL;
+  if (L->flags & ~(uint32_t)(ZSORT_LEARNED_DIRECT | ZSORT_LEARNED_ZSCORE_DIAG | ZSORT_LEARNED_VERIFY))
+    return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 
@@ -993,7 +995,7 @@ int zsort_default_learned_config(zsort_learned_config* lcfg) {
   std::memset(lcfg, 0, sizeof *lcfg);
   lcfg->buckets = 4096;
   lcfg->sample_stride = 100;
-  lcfg->steps = 32;
+  lcfg->steps = 16;
   lcfg->batches = 64;
   lcfg->lr = 1e-4;
   lcfg->seed = 0x5A17ull;
@@ -1016,9 +1018,11 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (rc) return rc;
   if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
   uint32_t* host_counts = report ? report->counts : nullptr;
+  zsort_mlp_params* params_out = report ? report->params_out : nullptr;
   if (report) {
     std::memset(report, 0, sizeof *report);
     report->counts = host_counts;
+    report->params_out = params_out;
   }
   if (n <= 1) return ZSORT_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -1048,7 +1052,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
       if (rc) return rc;
     }
     if (e == hipSuccess) e = zs::launch_lprep(lw->sample, m, lw->U, lw->Y, lw->res, st);
-    if (e == hipSuccess) e = zs::launch_linit(lw->sample, m, lw->par, st);
+    if (e == hipSuccess) e = zs::launch_linit(lw->sample, m, lw->par, lw->res, st);
     if (e == hipSuccess) e = zs::launch_ladam_reset(lw->adam, lw->res, st);
     if (e == hipSuccess && L.steps > 0) {
       // loss on minibatch 0 before and after training; the better parameters stay
@@ -1078,6 +1082,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   }
   const bool direct = (L.flags & ZSORT_LEARNED_DIRECT) != 0;
   if (e == hipSuccess && !direct) e = zs::launch_lthresh(lw->par, B, lw->res, lw->thr, st);
+  if (e == hipSuccess && !direct) e = zs::launch_lthr_check(lw->thr, lw->res, st);
   if (e == hipSuccess) e = hipEventRecord(lw->ev[1], st);
   if (e != hipSuccess) return hip_fail(e);
 
@@ -1117,13 +1122,17 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (e == hipSuccess) e = stage(w, w0, 0, zs::STAGE_HIST, grid_size(B, pw, w0.p.tile, zs::STAGE_HIST), st);
   if (e == hipSuccess)
     e = stage(w, w0, 0, zs::STAGE_SCATTER, grid_size(B, pw, w0.p.tile, zs::STAGE_SCATTER), st);
-  if (e == hipSuccess)
+  const bool scan = direct || (L.flags & ZSORT_LEARNED_VERIFY);
+  if (e == hipSuccess && scan)  // per-key inference: check the output itself
     e = zs::launch_lcheck(ws.keys[1], ws.bstart, n, B, lw->bmin, lw->bmax, lw->res,
                           std::max(1, g_cu_count) * 4, st);
+  if (e == hipSuccess && !scan) e = zs::launch_lmaxcount(ws.bstart, n, B, &lw->res->maxc, st);
   if (e == hipSuccess && host_counts) e = zs::launch_lcounts(ws.bstart, n, B, lw->counts, st);
   if (e == hipSuccess) e = hipEventRecord(lw->ev[3], st);
   if (e == hipSuccess && host_counts)
     e = hipMemcpyAsync(host_counts, lw->counts, (size_t)B * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && params_out)
+    e = hipMemcpyAsync(params_out, lw->par, sizeof(zs::MlpP), hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(lw->h_res, lw->res, sizeof(zs::LRes), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(lw->ev[4], st);
@@ -1131,7 +1140,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (e != hipSuccess) return hip_fail(e);
   const zs::LRes r = *lw->h_res;
   const double kp = 8.0 + pw;
-  double extra = 4.0 * (double)n + 8.0 * (double)n;  // cluster ids (write + read), check pass
+  double extra = 4.0 * (double)n + (scan ? 8.0 * (double)n : 0.0);  // cluster ids, key check
   if (r.fail) {
     // 4a. the map broke the cluster order: the z-score path sorts the
     //     caller's keys, which the first pass left untouched
@@ -1161,6 +1170,8 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
     report->thresholds = direct ? -1 : (int32_t)r.nt;
     report->steps = L.params ? 0 : (int32_t)r.steps_done;
     report->trained = (!L.params && L.steps > 0) ? (int32_t)r.trained : 0;
+    report->smin_out = r.smin;
+    report->smax_out = r.smax;
     report->sample_max_init = r.smax_init;
     report->sample_max_trained = r.smax_trained;
     report->sample_keys = m;
@@ -1234,7 +1245,10 @@ int zsort_mlp_init(const uint64_t* sorted_sample, size_t m, zsort_mlp_params* pa
   if (!sorted_sample || !params_out || m < 2 || m > 0x7FFFFFFFull) return ZSORT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = zs::launch_linit(sorted_sample, m, (zs::MlpP*)params_out, st);
+  LearnedWs* lw = nullptr;
+  int rc = lacquire(st, 0, 0, 0, &lw);
+  if (rc) return rc;
+  hipError_t e = zs::launch_linit(sorted_sample, m, (zs::MlpP*)params_out, lw->res, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e == hipSuccess ? ZSORT_OK : hip_fail(e);
 }

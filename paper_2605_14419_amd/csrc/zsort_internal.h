@@ -140,6 +140,8 @@ struct LRes {
   uint32_t trained;              // 1: the trained parameters were kept (not the initial ones)
   uint32_t pad;
   uint32_t smax_init, smax_trained;  // largest cluster of the sample under each parameter set
+  double iscore[28];             // initialisation: largest gap / key range of each sample block
+  uint64_t icut[28];             // and the position of that gap
 };
 
 // learned map of the first pass

@@ -24,9 +24,10 @@
 //   compile  -- for b = 1..nt the threshold t_b, the least key whose cluster
 //               is >= b, by bisection over the 64-bit keys; the first pass
 //               then finds a key's cluster by binary search in LDS;
-//   check    -- after the first pass, max(cluster j) <= min(every later
-//               cluster) is verified on the device; the caller falls back to
-//               the z-score map when it fails.
+//   check    -- max(cluster j) <= min(every later cluster) is verified on
+//               the device (sorted thresholds imply it; with per-key
+//               inference the first pass's output is scanned); the caller
+//               falls back to the z-score map when it fails.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -110,82 +111,93 @@ __global__ void k_lset_range(LRes* res, uint64_t smin, uint64_t smax) {
 // through by the second layer and weighed by its share (b - a + 1) / m in
 // the output: the sample CDF, linear inside a piece, flat between pieces.
 constexpr int kNBlk = 28, kNSplit = 4;
+static_assert(kNBlk == sizeof(LRes::iscore) / sizeof(double), "block count");
 
-__global__ void __launch_bounds__(kBlock) k_linit(const uint64_t* __restrict__ s, uint64_t m,
-                                                  MlpP* __restrict__ par) {
-  __shared__ double score[kNBlk];
-  __shared__ uint64_t cut[kNBlk];
+__device__ __forceinline__ void init_block_range(uint64_t i, uint64_t m, uint64_t& a, uint64_t& b) {
+  a = (i * m) / kNBlk;
+  b = ((i + 1) * m) / kNBlk;
+}
+
+// one workgroup per sample block: the block's largest gap (first position
+// on ties) relative to its key range
+__global__ void __launch_bounds__(kBlock) k_linit_gaps(const uint64_t* __restrict__ s, uint64_t m,
+                                                       LRes* res) {
   __shared__ double rv[kWaves];
   __shared__ uint64_t rj[kWaves];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, i = blockIdx.x;
   const uint64_t smin = s[0], smax = s[m - 1];
-  uint32_t* z = reinterpret_cast<uint32_t*>(par);
-  for (uint32_t i = t; i < sizeof(MlpP) / 4; i += blockDim.x) z[i] = 0u;
-  for (int i = 0; i < kNBlk; ++i) {
-    const uint64_t a = ((uint64_t)i * m) / kNBlk, b = ((uint64_t)(i + 1) * m) / kNBlk;
-    double span = 0.0;
-    if (b - a >= 2) span = __dsub_rn(mlp_norm(s[b - 1], smin, smax), mlp_norm(s[a], smin, smax));
-    if (!(span > 0.0)) {
-      if (t == 0) {
-        score[i] = 0.0;
-        cut[i] = 0;
-      }
-      continue;
-    }
-    // largest gap, first position on ties
-    double best = -1.0;
-    uint64_t bj = 0;
-    for (uint64_t j = a + t; j + 1 < b; j += kBlock) {
-      const double g = __dsub_rn(mlp_norm(s[j + 1], smin, smax), mlp_norm(s[j], smin, smax));
-      if (g > best) {
-        best = g;
-        bj = j;
-      }
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
-      const uint64_t oj = __shfl_xor(bj, o);
-      if (ov > best || (ov == best && oj < bj)) {
-        best = ov;
-        bj = oj;
-      }
-    }
-    if ((t & (kWave - 1)) == 0) {
-      rv[t / kWave] = best;
-      rj[t / kWave] = bj;
-    }
-    __syncthreads();
+  uint64_t a, b;
+  init_block_range((uint64_t)i, m, a, b);
+  double span = 0.0;
+  if (b - a >= 2) span = __dsub_rn(mlp_norm(s[b - 1], smin, smax), mlp_norm(s[a], smin, smax));
+  if (!(span > 0.0)) {
     if (t == 0) {
-      for (int w = 1; w < kWaves; ++w)
-        if (rv[w] > best || (rv[w] == best && rj[w] < bj)) {
-          best = rv[w];
-          bj = rj[w];
-        }
-      score[i] = __ddiv_rn(best, span);
-      cut[i] = bj;
+      res->iscore[i] = 0.0;
+      res->icut[i] = 0;
     }
-    __syncthreads();
+    return;
+  }
+  double best = -1.0;
+  uint64_t bj = 0;
+  for (uint64_t j = a + t; j + 1 < b; j += kBlock) {
+    const double g = __dsub_rn(mlp_norm(s[j + 1], smin, smax), mlp_norm(s[j], smin, smax));
+    if (g > best) {
+      best = g;
+      bj = j;
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o);
+    const uint64_t oj = __shfl_xor(bj, o);
+    if (ov > best || (ov == best && oj < bj)) {
+      best = ov;
+      bj = oj;
+    }
+  }
+  if ((t & (kWave - 1)) == 0) {
+    rv[t / kWave] = best;
+    rj[t / kWave] = bj;
   }
   __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kWaves; ++w)
+      if (rv[w] > best || (rv[w] == best && rj[w] < bj)) {
+        best = rv[w];
+        bj = rj[w];
+      }
+    res->iscore[i] = __ddiv_rn(best, span);
+    res->icut[i] = bj;
+  }
+}
+
+// the pieces and the parameters (one workgroup)
+__global__ void k_linit(const uint64_t* __restrict__ s, uint64_t m, const LRes* res,
+                        MlpP* __restrict__ par) {
+  const int t = threadIdx.x;
+  uint32_t* z = reinterpret_cast<uint32_t*>(par);
+  for (uint32_t i = t; i < sizeof(MlpP) / 4; i += blockDim.x) z[i] = 0u;
+  __syncthreads();
   if (t != 0) return;
+  const uint64_t smin = s[0], smax = s[m - 1];
   bool split[kNBlk];
   for (int i = 0; i < kNBlk; ++i) split[i] = false;
   for (int k = 0; k < kNSplit; ++k) {
     int bi = -1;
     for (int i = 0; i < kNBlk; ++i)
-      if (!split[i] && score[i] > 0.5 && (bi < 0 || score[i] > score[bi])) bi = i;
+      if (!split[i] && res->iscore[i] > 0.5 && (bi < 0 || res->iscore[i] > res->iscore[bi])) bi = i;
     if (bi < 0) break;
     split[bi] = true;
   }
   int r = 0;
   for (int i = 0; i < kNBlk; ++i) {
-    const uint64_t a = ((uint64_t)i * m) / kNBlk, b = ((uint64_t)(i + 1) * m) / kNBlk;
+    uint64_t a, b;
+    init_block_range((uint64_t)i, m, a, b);
     if (a == b) continue;
     const int np = split[i] ? 2 : 1;
     for (int q = 0; q < np; ++q, ++r) {
-      const uint64_t pa = (split[i] && q == 1) ? cut[i] + 1 : a;
-      const uint64_t pb = (split[i] && q == 0) ? cut[i] : b - 1;
+      const uint64_t pa = (split[i] && q == 1) ? res->icut[i] + 1 : a;
+      const uint64_t pb = (split[i] && q == 0) ? res->icut[i] : b - 1;
       const double ua = mlp_norm(s[pa], smin, smax), ub = mlp_norm(s[pb], smin, smax);
       const double w = ub > ua ? __ddiv_rn(1.0, __dsub_rn(ub, ua)) : 4503599627370496.0;  // 2^52
       par->w1[r] = w;
@@ -497,46 +509,86 @@ __global__ void __launch_bounds__(kBlock) k_lkeep(MlpP* __restrict__ par,
 }
 
 // ---------------------------------------------------------------------------
-// order check after the first pass.  y holds the keys grouped by cluster,
-// cluster b at [bst[b], bst[b+1]) (the last one up to n).
+// order checks.
+// Thresholds: if t_1 <= t_2 <= ... <= t_nt, the cluster #{b : t_b <= x} is
+// non-decreasing in x, so every key of cluster j lies below t_(j+1) and
+// every key of a later cluster at or above it: max(C_j) <= min(C_j') for all
+// j < j'.  The check is that the thresholds are sorted.
+// Keys (per-key inference): y holds the first pass's output, cluster b at
+// [bst[b], bst[b+1]) (the last one up to n); per-cluster minima and maxima
+// are taken in chunks of the output and combined with 64-bit atomics.
 // ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_lthr_check(const uint64_t* __restrict__ thr,
+                                                       LRes* res) {
+  __shared__ uint32_t bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const uint32_t nt = res->nt;
+  uint32_t my = 0;
+  for (uint32_t b = threadIdx.x; b + 1 < nt; b += kBlock)
+    if (thr[b] > thr[b + 1]) my = 1;
+  if (my) atomicOr(&bad, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) res->fail = bad;
+}
+
+__global__ void k_lminmax_init(uint64_t* __restrict__ bmin, uint64_t* __restrict__ bmax, int B) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    bmin[b] = ~0ull;   // an empty cluster never sits below a later maximum
+    bmax[b] = 0;
+  }
+}
+
+constexpr uint64_t kCheckChunk = 16384;
+
 __global__ void __launch_bounds__(kBlock) k_lminmax(const uint64_t* __restrict__ y,
                                                     const uint32_t* __restrict__ bst, uint64_t n,
                                                     int B, uint64_t* __restrict__ bmin,
                                                     uint64_t* __restrict__ bmax) {
   __shared__ uint64_t rmn[kWaves], rmx[kWaves];
   const int t = threadIdx.x;
-  for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    // clamped, so that a first pass that hit a device-side limit (and left
-    // inconsistent starts) still reads inside the array
-    const uint64_t a = min((uint64_t)bst[b], n);
-    const uint64_t z = max(a, min((b + 1 < B) ? (uint64_t)bst[b + 1] : n, n));
-    uint64_t mn = ~0ull, mx = 0;
-    for (uint64_t i = a + t; i < z; i += kBlock) {
-      const uint64_t v = y[i];
-      mn = v < mn ? v : mn;
-      mx = v > mx ? v : mx;
+  // cluster starts, clamped, so that a first pass that hit a device-side
+  // limit (and left inconsistent starts) still reads inside the array
+  auto start = [&](int b) -> uint64_t { return b < B ? min((uint64_t)bst[b], n) : n; };
+  for (uint64_t c0 = blockIdx.x * kCheckChunk; c0 < n; c0 += gridDim.x * kCheckChunk) {
+    const uint64_t c1 = min(c0 + kCheckChunk, n);
+    // last cluster starting at or before c0
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (start(mid) <= c0) lo = mid; else hi = mid - 1;
     }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      const uint64_t a2 = __shfl_xor(mn, o), b2 = __shfl_xor(mx, o);
-      mn = a2 < mn ? a2 : mn;
-      mx = b2 > mx ? b2 : mx;
-    }
-    if ((t & (kWave - 1)) == 0) {
-      rmn[t / kWave] = mn;
-      rmx[t / kWave] = mx;
-    }
-    __syncthreads();
-    if (t == 0) {
-      for (int w = 1; w < kWaves; ++w) {
-        mn = rmn[w] < mn ? rmn[w] : mn;
-        mx = rmx[w] > mx ? rmx[w] : mx;
+    for (int b = lo; b < B && start(b) < c1; ++b) {
+      const uint64_t a = max(c0, start(b));
+      const uint64_t z = min(c1, max(start(b), start(b + 1)));
+      if (a >= z) continue;   // uniform: every thread sees the same bounds
+      uint64_t mn = ~0ull, mx = 0;
+      for (uint64_t i = a + t; i < z; i += kBlock) {
+        const uint64_t v = y[i];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
       }
-      bmin[b] = mn;   // empty cluster: all ones, never below a later maximum
-      bmax[b] = mx;
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint64_t a2 = __shfl_xor(mn, o), b2 = __shfl_xor(mx, o);
+        mn = a2 < mn ? a2 : mn;
+        mx = b2 > mx ? b2 : mx;
+      }
+      if ((t & (kWave - 1)) == 0) {
+        rmn[t / kWave] = mn;
+        rmx[t / kWave] = mx;
+      }
+      __syncthreads();
+      if (t == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+          mn = rmn[w] < mn ? rmn[w] : mn;
+          mx = rmx[w] > mx ? rmx[w] : mx;
+        }
+        atomicMin((unsigned long long*)&bmin[b], (unsigned long long)mn);
+        atomicMax((unsigned long long*)&bmax[b], (unsigned long long)mx);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -626,8 +678,9 @@ hipError_t launch_lset_range(LRes* res, uint64_t smin, uint64_t smax, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_linit(const uint64_t* s, uint64_t m, MlpP* par, hipStream_t st) {
-  hipLaunchKernelGGL(k_linit, dim3(1), dim3(kBlock), 0, st, s, m, par);
+hipError_t launch_linit(const uint64_t* s, uint64_t m, MlpP* par, LRes* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_linit_gaps, dim3(kNBlk), dim3(kBlock), 0, st, s, m, res);
+  hipLaunchKernelGGL(k_linit, dim3(1), dim3(64), 0, st, s, m, (const LRes*)res, par);
   return hipGetLastError();
 }
 
@@ -686,9 +739,16 @@ hipError_t launch_lkeep(MlpP* par, const MlpP* par0, const double* g0, const dou
 
 hipError_t launch_lcheck(const uint64_t* y, const uint32_t* bst, uint64_t n, int B, uint64_t* bmin,
                          uint64_t* bmax, LRes* res, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_lminmax, dim3(std::min(grid, B)), dim3(kBlock), 0, st, y, bst, n, B, bmin,
-                     bmax);
+  hipLaunchKernelGGL(k_lminmax_init, dim3((B + 255) / 256), dim3(256), 0, st, bmin, bmax, B);
+  const uint64_t chunks = (n + kCheckChunk - 1) / kCheckChunk;
+  const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, (uint64_t)grid));
+  hipLaunchKernelGGL(k_lminmax, dim3(blocks), dim3(kBlock), 0, st, y, bst, n, B, bmin, bmax);
   hipLaunchKernelGGL(k_lcheck, dim3(1), dim3(kBlock), 0, st, bmin, bmax, bst, n, B, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_lthr_check(const uint64_t* thr, LRes* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_lthr_check, dim3(1), dim3(kBlock), 0, st, thr, res);
   return hipGetLastError();
 }
 

@@ -205,7 +205,7 @@ def test_learned_sort_matches_oracle(wl, n, pw):
     say(f"case learned sort {wl} n={n} pw={pw}")
     ok, op, rep, st = learned_sort(keys, pay, CFG, dict(buckets=4096))
     assert rep["used_learned"] == 1 and rep["fallback"] == 0, rep
-    assert rep["steps"] == 32 and rep["thresholds"] > 0
+    assert rep["steps"] == 16 and rep["thresholds"] > 0
     # the parameters with the smaller largest sample cluster are kept
     kept = rep["sample_max_trained"] if rep["trained"] else rep["sample_max_init"]
     assert kept <= rep["sample_max_init"] and kept <= rep["sample_max_trained"]
@@ -221,7 +221,7 @@ def test_first_pass_histogram_matches_oracle_with_given_params(mix):
     nt, thr = oracle.mlp_thresholds(p2, smin, smax, 4096)
     want = np.bincount(np.searchsorted(thr[:nt], keys, side="right"), minlength=4096)
     ek, ei, _ = oracle.sort(keys, idx, k=1024, cutoff=2048, max_zlevels=8)
-    for flags in (0, zs.ZSORT_LEARNED_DIRECT):
+    for flags in (0, zs.ZSORT_LEARNED_DIRECT, zs.ZSORT_LEARNED_VERIFY):
         say(f"case given params flags={flags}")
         lc = dict(buckets=4096, params=dpar(p2), smin=smin, smax=smax, flags=flags)
         ok, op, rep, _ = learned_sort(keys, idx, CFG, lc, counts=True)
@@ -237,11 +237,19 @@ def test_fallback_when_the_map_breaks_the_order(mix):
     p = oracle.mlp_init(s, smin, smax)
     p[oracle.W3:oracle.W3 + 32] = -1.0 / 32     # f decreasing: clusters in reverse order
     p[oracle.B3] = 1.0
-    say("case fallback")
+    ek, ei, _ = oracle.sort(keys, idx, k=1024, cutoff=2048, max_zlevels=8)
+    say("case fallback direct")
     lc = dict(buckets=1024, params=dpar(p), smin=smin, smax=smax, flags=zs.ZSORT_LEARNED_DIRECT)
     ok, op, rep, st = learned_sort(keys, idx, CFG, lc)
     assert rep["fallback"] == 1 and rep["used_learned"] == 0, rep
-    ek, ei, _ = oracle.sort(keys, idx, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(ok, ek) and np.array_equal(op, ei)
+    # thresholds of a decreasing map: the bisection finds the first key with
+    # cluster >= b, the thresholds come out unsorted unless all are equal;
+    # either the check rejects them or the map they define is monotone
+    say("case fallback thresholds")
+    lc = dict(buckets=1024, params=dpar(p), smin=smin, smax=smax)
+    ok, op, rep, st = learned_sort(keys, idx, CFG, lc)
+    assert rep["fallback"] + rep["used_learned"] == 1, rep
     assert np.array_equal(ok, ek) and np.array_equal(op, ei)
 
 
@@ -276,3 +284,23 @@ def test_small_inputs_take_the_plain_path():
         order = np.argsort(keys, kind="stable")
         assert np.array_equal(host_u64(tk), keys[order])
         assert np.array_equal(tp.cpu().numpy().view(np.uint32), idx[order])
+
+
+def test_reused_parameters_reproduce_the_first_pass(mix):
+    """parameters handed out by one call and given to the next reproduce the
+    first pass exactly (no sample, no training)"""
+    keys, idx, _ = mix
+    say("case reuse")
+    par = torch.empty(zs.MLP_PARAMS_BYTES, dtype=torch.uint8, device=DEV)
+    tk, tp = dkeys(keys), torch.from_numpy(idx.view(np.int32)).to(DEV)
+    r1 = zs.zsort_stable_learned(tk, tp, CFG, dict(buckets=2048), counts=True, params_out=par)
+    first = (host_u64(tk), tp.cpu().numpy().view(np.uint32))
+    tk, tp = dkeys(keys), torch.from_numpy(idx.view(np.int32)).to(DEV)
+    r2 = zs.zsort_stable_learned(tk, tp, CFG, dict(buckets=2048, params=par, smin=r1["smin_out"],
+                                                   smax=r1["smax_out"]), counts=True)
+    assert r1["used_learned"] == r2["used_learned"] == 1 and r2["steps"] == 0
+    assert np.array_equal(r1["counts"], r2["counts"])
+    assert np.array_equal(host_u64(tk), first[0])
+    assert np.array_equal(tp.cpu().numpy().view(np.uint32), first[1])
+    ek, ei, _ = oracle.sort(keys, idx, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(first[0], ek) and np.array_equal(first[1], ei)
