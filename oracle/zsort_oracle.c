@@ -59,8 +59,14 @@
  *   sigma = sqrt(var); Zmin = |(0 - m) / sigma|; scale = k / 4
  *   A = scale / sigma; B = Zmin * scale
  *
- * Parity pins for each function are in tests/test_oracle_pins.py; none of the
- * functions here is "parity unpinned".
+ * Learned partition map (an extension the paper does not have; last section
+ * of this file): a monotone MLP 1 -> 32 -> 32 -> 1 fitted to a key sample's
+ * CDF -- inference in a fixed precision, cluster ids, thresholds by
+ * bisection, the gap-aware piecewise initialisation, the exact binary64
+ * squared-error gradient and Adam training.
+ *
+ * Parity pins for each function are in tests/test_oracle_pins.py and
+ * tests/test_oracle_mlp.py; none of the functions here is "parity unpinned".
  */
 #include <stdint.h>
 #include <stdlib.h>
