@@ -25,6 +25,9 @@ hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st
 int stage_blocks_per_cu(int k, int pw, int tile, int stage);
 // learned partition map (zsort_learned.hip)
 hipError_t launch_init_learned(const Ws& ws, uint64_t n, hipStream_t st);
+hipError_t launch_reset_lists(const Ws& ws, int slot, hipStream_t st);
+hipError_t launch_lfine_hist(const uint64_t* x, uint64_t n, const uint64_t* thr, const LRes* res,
+                             int B, uint32_t* counts, hipStream_t st);
 hipError_t launch_lsample(const uint64_t* x, uint64_t m, uint32_t stride, uint64_t seed,
                           uint64_t* out, hipStream_t st);
 hipError_t launch_lprep(const uint64_t* s, uint64_t m, double* U, float* Y, LRes* res,
@@ -565,8 +568,8 @@ struct LearnedWs {
   double* gout1 = nullptr;
   uint32_t* counts = nullptr;
   uint32_t* hc = nullptr;  // sample cluster sizes: [0] initial, [1] trained parameters
-  zs::LRes* h_res = nullptr;  // pinned
-  hipEvent_t ev[5] = {};
+  zs::LRes* h_res = nullptr;  // pinned, 2 records: at the order check, after the learned passes
+  hipEvent_t ev[6] = {};
 };
 std::unordered_map<hipStream_t, LearnedWs*> g_lws;
 
@@ -582,11 +585,11 @@ int lacquire(hipStream_t st, uint64_t n, uint64_t m, size_t part_floats, Learned
   w->device = dev;
   if (!w->h_res) {
     void* p = nullptr;
-    e = hipHostMalloc(&p, sizeof(zs::LRes), hipHostMallocDefault);
+    e = hipHostMalloc(&p, 2 * sizeof(zs::LRes), hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e);
     w->h_res = (zs::LRes*)p;
   }
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 6; ++i)
     if (!w->ev[i]) {
       e = hipEventCreate(&w->ev[i]);
       if (e != hipSuccess) return hip_fail(e);
@@ -1086,11 +1089,16 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (e == hipSuccess) e = hipEventRecord(lw->ev[1], st);
   if (e != hipSuccess) return hip_fail(e);
 
-  // 2. the main workspace, sized for a first pass of B clusters
+  // 2. the main workspace.  More than 512 clusters (a multiple of 64) are
+  //    made in two stages of the same thresholds: 64 root clusters (every
+  //    (B/64)-th threshold), then B/64 sub-clusters of each, so that each
+  //    scatter writes long runs; the clusters are those of one B-way pass.
+  const bool two = !direct && B > 512 && B % 64 == 0;
+  const int B0 = two ? 64 : B, B1 = two ? B / 64 : 0;
   Shape s;
   s.n = n;
   s.pw = payload_bytes;
-  s.k = c.k;
+  s.k = std::max(c.k, B1);
   s.cutoff = c.cutoff;
   s.chunk = c.chunk;
   s.tile = c.tile;
@@ -1100,12 +1108,14 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (rc) return rc;
   if (!pacing_ready(w)) return ZSORT_EHIP;
   const Ws ws = make_ws(w, keys, pay, c, payload_bytes);
-  const Ws w0 = first_pass_ws(ws, lw, B, direct);
+  Ws w0 = first_pass_ws(ws, lw, B0, direct);
+  w0.lm.sub = (uint32_t)B1;
+  const Ws w1 = first_pass_ws(ws, lw, two ? B1 : B0, false);
   const int pw = payload_bytes;
   if (L.flags & ZSORT_LEARNED_ZSCORE_DIAG) {
-    // the z-score map's histogram at the same cluster count (moments,
-    // statistics, histogram of the root; nothing moves)
-    Ws wd = w0;
+    // the z-score map's histogram at B clusters (moments, statistics,
+    // histogram of the root; nothing moves)
+    Ws wd = first_pass_ws(ws, lw, B, false);
     std::memset(&wd.lm, 0, sizeof wd.lm);
     e = zs::launch_reset(wd, st);
     if (e == hipSuccess) e = zs::launch_init_single(wd, n, st);
@@ -1115,20 +1125,29 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
     if (e != hipSuccess) return hip_fail(e);
   }
   // 3. learned first pass (hist writes the cluster ids, scatter moves key +
-  //    payload to the alternate buffer), then the order check
-  e = zs::launch_reset(ws, st);
-  if (e == hipSuccess) e = zs::launch_init_learned(ws, n, st);
+  //    payload to the alternate buffer); the caller's keys stay untouched
+  //    until the order check has been read
+  e = zs::launch_reset(w0, st);
+  if (e == hipSuccess) e = zs::launch_init_learned(w0, n, st);
   if (e == hipSuccess) e = hipEventRecord(lw->ev[2], st);
-  if (e == hipSuccess) e = stage(w, w0, 0, zs::STAGE_HIST, grid_size(B, pw, w0.p.tile, zs::STAGE_HIST), st);
   if (e == hipSuccess)
-    e = stage(w, w0, 0, zs::STAGE_SCATTER, grid_size(B, pw, w0.p.tile, zs::STAGE_SCATTER), st);
+    e = stage(w, w0, 0, zs::STAGE_HIST, grid_size(B0, pw, w0.p.tile, zs::STAGE_HIST), st);
+  if (e == hipSuccess)
+    e = stage(w, w0, 0, zs::STAGE_SCATTER, grid_size(B0, pw, w0.p.tile, zs::STAGE_SCATTER), st);
   const bool scan = direct || (L.flags & ZSORT_LEARNED_VERIFY);
-  if (e == hipSuccess && scan)  // per-key inference: check the output itself
-    e = zs::launch_lcheck(ws.keys[1], ws.bstart, n, B, lw->bmin, lw->bmax, lw->res,
+  if (e == hipSuccess && scan)  // check the output itself (root clusters)
+    e = zs::launch_lcheck(ws.keys[1], ws.bstart, n, B0, lw->bmin, lw->bmax, lw->res,
                           std::max(1, g_cu_count) * 4, st);
-  if (e == hipSuccess && !scan) e = zs::launch_lmaxcount(ws.bstart, n, B, &lw->res->maxc, st);
-  if (e == hipSuccess && host_counts) e = zs::launch_lcounts(ws.bstart, n, B, lw->counts, st);
-  if (e == hipSuccess) e = hipEventRecord(lw->ev[3], st);
+  if (e == hipSuccess && host_counts) {
+    if (two) {
+      e = hipMemsetAsync(lw->counts, 0, (size_t)B * 4, st);
+      if (e == hipSuccess)
+        e = zs::launch_lfine_hist(ws.keys[1], n, lw->thr, lw->res, B, lw->counts, st);
+    } else {
+      e = zs::launch_lcounts(ws.bstart, n, B, lw->counts, st);
+    }
+  }
+  if (e == hipSuccess && !two) e = hipEventRecord(lw->ev[3], st);
   if (e == hipSuccess && host_counts)
     e = hipMemcpyAsync(host_counts, lw->counts, (size_t)B * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && params_out)
@@ -1140,15 +1159,29 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   if (e != hipSuccess) return hip_fail(e);
   const zs::LRes r = *lw->h_res;
   const double kp = 8.0 + pw;
-  double extra = 4.0 * (double)n + (scan ? 8.0 * (double)n : 0.0);  // cluster ids, key check
+  // cluster ids (written by hist, read by scatter) of each learned pass, key check
+  double extra = (two ? 8.0 : 4.0) * (double)n + (scan ? 8.0 * (double)n : 0.0);
   if (r.fail) {
     // 4a. the map broke the cluster order: the z-score path sorts the
     //     caller's keys, which the first pass left untouched
     e = enqueue(w, ws, call, st);
-    extra += (8.0 + 2.0 * kp) * (double)n;  // the discarded first pass
+    extra = 4.0 * (double)n + (scan ? 8.0 * (double)n : 0.0) + (8.0 + 2.0 * kp) * (double)n;
   } else {
-    // 4b. local sort of the first pass's small clusters, then the z-score
-    //     levels 1, 2, ... on the large ones
+    // z-score levels after the learned passes: clusters hold about n / B
+    // keys, so fewer clusters per pass suffice to reach the cutoff (about 4
+    // times n / (B * cutoff), a power of two in [16, k])
+    int k2 = 16;
+    while (k2 < c.k && (double)k2 < 4.0 * (double)n / ((double)B * (double)c.cutoff)) k2 <<= 1;
+    k2 = std::min(k2, c.k);
+    Ws wz = ws;
+    wz.p.k = k2;
+    wz.p.lb = floor_log2(k2);
+    Call cz = call;
+    cz.cfg.k = k2;
+    if (cz.cfg.tile == 4096 && k2 > 1024) cz.cfg.tile = wz.p.tile = 2048;
+    // 4b. local sort of the first pass's small clusters; with two stages the
+    //     second learned pass (its lists start empty: no moments pass runs
+    //     for learned segments); then the z-score levels on what is left
     e = stage(w, ws, 0, zs::STAGE_LOCAL, grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL), st);
     if (e == hipSuccess)
       e = stage(w, ws, 0, zs::STAGE_LOCAL_HARD, grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL_HARD), st);
@@ -1156,7 +1189,29 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
       e = hipMemcpyAsync(&w->h_nseg[1], &ws.ctl->nseg[1], sizeof(uint32_t), hipMemcpyDeviceToHost,
                          st);
     if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[0], st);
-    if (e == hipSuccess) e = enqueue_levels(w, ws, call, st, 1);
+    if (two) {
+      if (e == hipSuccess) e = zs::launch_reset_lists(ws, 0, st);
+      if (e == hipSuccess)
+        e = stage(w, w1, 1, zs::STAGE_HIST, grid_size(B1, pw, w1.p.tile, zs::STAGE_HIST), st);
+      if (e == hipSuccess)
+        e = stage(w, w1, 1, zs::STAGE_SCATTER, grid_size(B1, pw, w1.p.tile, zs::STAGE_SCATTER), st);
+      if (e == hipSuccess) e = hipEventRecord(lw->ev[3], st);
+      if (e == hipSuccess && report)  // the largest cluster, complete after the second pass
+        e = hipMemcpyAsync(lw->h_res + 1, lw->res, sizeof(zs::LRes), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(lw->ev[5], st);
+      if (e == hipSuccess)
+        e = stage(w, ws, 1, zs::STAGE_LOCAL, grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL), st);
+      if (e == hipSuccess)
+        e = stage(w, ws, 1, zs::STAGE_LOCAL_HARD,
+                  grid_size(c.k, pw, c.tile, zs::STAGE_LOCAL_HARD), st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&w->h_nseg[2], &ws.ctl->nseg[0], sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[1], st);
+      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 2);
+    } else {
+      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 1);
+    }
   }
   if (e != hipSuccess) return hip_fail(e);
   w->calls++;
@@ -1165,6 +1220,12 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   w->has_last = true;
   w->last_extra_bytes = extra;
   if (report) {
+    uint64_t maxc = r.maxc;
+    if (two && !r.fail) {
+      e = hipEventSynchronize(lw->ev[5]);
+      if (e != hipSuccess) return hip_fail(e);
+      maxc = lw->h_res[1].maxc;
+    }
     report->used_learned = r.fail ? 0 : 1;
     report->fallback = r.fail ? 1 : 0;
     report->thresholds = direct ? -1 : (int32_t)r.nt;
@@ -1175,10 +1236,10 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
     report->sample_max_init = r.smax_init;
     report->sample_max_trained = r.smax_trained;
     report->sample_keys = m;
-    report->max_cluster_learned = r.maxc;
+    report->max_cluster_learned = maxc;
     report->max_cluster_zscore = r.maxz;
     const double mean = (double)n / (double)B;
-    report->imbalance_learned = (double)r.maxc / mean;
+    report->imbalance_learned = (double)maxc / mean;
     report->imbalance_zscore = (L.flags & ZSORT_LEARNED_ZSCORE_DIAG) ? (double)r.maxz / mean : 0.0;
     report->loss_first = r.loss_first;
     report->loss_last = r.loss_last;

@@ -52,16 +52,16 @@ struct __attribute__((aligned(16))) Seg {
   uint32_t first_work;   // first chunk's index in the level's work list
   uint32_t nchunks;
   uint32_t status_base;  // first look-back slot (segments of > 1 chunk)
-  uint32_t pad1;
+  uint32_t lm_base;      // learned map: first threshold of this segment's window
   int32_t parent;        // index of the parent in the previous level's list
-  int32_t pad0;
+  uint32_t lm_cnt;       // learned map: thresholds in the window (stride in `shift`)
   // results of finalize
   uint64_t o, M;
   uint64_t s1[2];        // sum (x - o)
   uint64_t s2[4];        // sum (x - o)^2
   double m, sigma, zmin, A, B;
   int32_t kind;
-  int32_t shift;         // range-map shift
+  int32_t shift;         // range-map shift; learned map: threshold stride of the window
 };
 
 struct __attribute__((aligned(16))) Leaf {
@@ -145,13 +145,19 @@ struct LRes {
 };
 
 // learned map of the first pass
+// A learned segment's clusters are counted against a window of the
+// thresholds: lm_cnt of them, starting at thr[lm_base], every shift-th one.
+// With two stages (sub > 0) the root's window is every sub-th threshold and
+// each root cluster j becomes a learned child with the sub - 1 thresholds
+// after thr[j * sub - 1], so that the two passes together give the clusters
+// of all thresholds.
 struct LMap {
   const uint64_t* thr;   // thresholds t_1..t_nt: t_b is the least key whose cluster is >= b
   const MlpP* par;       // parameters (direct per-key inference only)
   uint16_t* ids;         // cluster id of each key, written by hist, read by scatter
-  const LRes* res;       // normalisation range and threshold count
+  LRes* res;             // normalisation range, threshold count, largest cluster
   int32_t direct;        // 1: evaluate the MLP per key instead of searching the thresholds
-  int32_t pad;
+  uint32_t sub;          // two stages: clusters per root cluster (0: one stage)
 };
 
 struct Params {

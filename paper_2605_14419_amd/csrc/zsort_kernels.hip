@@ -423,6 +423,15 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
     ws.work[0][i] = (uint64_t)i;  // segment 0, chunk i
 }
 
+// empties the lists of one slot (a level that runs no moments pass)
+__global__ void k_reset_lists(Ws ws, int slot) {
+  Ctl* c = ws.ctl;
+  if (threadIdx.x == 0) {
+    c->nseg[slot] = 0; c->nwork[slot] = 0; c->nleaf[slot] = 0; c->nleafw[slot] = 0;
+    c->nhard[slot] = 0; c->nstatus[slot] = 0;
+  }
+}
+
 // one array [0, n), n > cutoff, whose first pass uses the learned map
 __global__ void k_init_learned(Ws ws, uint64_t n) {
   Ctl* c = ws.ctl;
@@ -435,6 +444,11 @@ __global__ void k_init_learned(Ws ws, uint64_t n) {
     s.kind = KIND_LMAP;
     s.o = 0;
     s.M = ~0ull;
+    // window: every threshold, or with two stages every sub-th one
+    const uint32_t nt = ws.lm.res->nt, sub = ws.lm.sub;
+    s.lm_base = sub ? sub - 1 : 0;
+    s.lm_cnt = sub ? nt / sub : nt;
+    s.shift = sub ? (int32_t)sub : 1;
     c->nseg[0] = 1;
     c->nwork[0] = nch;
     c->nstatus[0] = nch > 1 ? nch : 0;
@@ -749,7 +763,8 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       if (n <= cutoff) continue;
       const uint32_t idx = sm.base_seg + sm.t0[b];
       Seg& cs = ws.segs[N][idx];
-      const bool crm = parent_r || (L + 1 >= ws.p.max_zlevels) || (uint64_t)n == sg.count;
+      const bool crm = !(parent_l && ws.lm.sub) &&
+                       (parent_r || (L + 1 >= ws.p.max_zlevels) || (uint64_t)n == sg.count);
       cs.start = sg.start + sm.bst[b];
       cs.count = n;
       cs.o_parent = sg.o;
@@ -768,6 +783,17 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       cs.status_base = sm.base_status + sm.t2[b];
       cs.parent = (int32_t)si;
       seg_clear_acc(cs);
+      if (parent_l && ws.lm.sub) {
+        // first stage of a two-stage learned map: the child is learned too,
+        // with the sub - 1 thresholds after root threshold b
+        const uint32_t sub = ws.lm.sub, nt = ws.lm.res->nt, base = (uint32_t)b * sub;
+        cs.flags = 0;
+        cs.kind = KIND_LMAP;
+        cs.M = ~0ull;
+        cs.lm_base = base;
+        cs.lm_cnt = nt > base ? min(nt - base, sub - 1) : 0u;
+        cs.shift = 1;
+      }
     }
     // work items of the children, in chunk order; t0 now maps child -> bucket
     __syncthreads();
@@ -852,6 +878,17 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   }
   __syncthreads();
 
+  // largest final cluster of the learned map (with two stages, root
+  // clusters that are not split again count whole)
+  if (parent_l) {
+    uint32_t mc = 0;
+    for (int b = t; b < k; b += kBlock) {
+      const uint32_t n = sm.h[b];
+      if (!ws.lm.sub || n <= cutoff) mc = n > mc ? n : mc;
+    }
+    if (mc) atomicMax((unsigned long long*)&ws.lm.res->maxc, (unsigned long long)mc);
+  }
+
   // statistics and trace
   if (t == 0) {
     atomicAdd((unsigned long long*)&c->lvl_keys[L], (unsigned long long)sg.count);
@@ -885,10 +922,10 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   __syncthreads();
 }
 
-// LM: the learned first pass (every segment has KIND_LMAP); a separate
-// instance so that the per-key MLP of its direct mode does not raise the
-// register count of the plain histogram
-template <int KMAX, bool LM>
+// LM: 0 plain; the learned passes (every segment has KIND_LMAP): 1 with
+// thresholds, 2 with the MLP evaluated per key.  Separate instances, so that
+// the per-key MLP does not raise the register count of the other two.
+template <int KMAX, int LM>
 __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   __shared__ HistSmem<KMAX> sm;
   Ctl* c = ws.ctl;
@@ -916,20 +953,24 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     for (int b = t; b < k; b += kBlock) sm.h[b] = 0;
     __syncthreads();
-    if constexpr (LM) {
-      // learned map: cluster = number of thresholds <= key (binary search in
-      // LDS), or the MLP evaluated per key; the ids go to the scatter pass
-      const uint32_t nt = min(ws.lm.res->nt, (uint32_t)(k - 1));
+    if constexpr (LM != 0) {
+      // learned map: cluster = number of the segment's window thresholds
+      // <= key (binary search in LDS), or the MLP evaluated per key; the ids
+      // go to the scatter pass
+      const uint32_t nt = min(sg.lm_cnt, (uint32_t)(k - 1));
+      const uint64_t* __restrict__ wthr = ws.lm.thr + sg.lm_base;
+      const uint32_t stride = (uint32_t)sg.shift;
       uint64_t* thr = reinterpret_cast<uint64_t*>(sm.t0);  // t0, t1: KMAX words
-      if (!ws.lm.direct)
-        for (uint32_t q = t; q < nt; q += kBlock) thr[q] = ws.lm.thr[q];
+      if constexpr (LM == 1)
+        for (uint32_t q = t; q < nt; q += kBlock) thr[q] = wthr[(uint64_t)q * stride];
       __syncthreads();
       const uint32_t top = top_pow2(nt);
       const uint64_t smin = ws.lm.res->smin, smax = ws.lm.res->smax;
       uint16_t* __restrict__ ids = ws.lm.ids;
       for_each_key<4>(x, beg, end, [&](uint64_t i, uint64_t v) {
-        const uint32_t b = ws.lm.direct ? mlp_cluster(*ws.lm.par, v, smin, smax, k)
-                                        : thr_cluster(thr, nt, top, v);
+        uint32_t b;
+        if constexpr (LM == 2) b = mlp_cluster(*ws.lm.par, v, smin, smax, k);
+        else b = thr_cluster(thr, nt, top, v);
         atomicAdd(&sm.h[b], 1u);
         ids[i] = (uint16_t)b;
       });
@@ -1693,7 +1734,7 @@ static const void* stage_fn(int stage) {
   switch (stage) {
     case STAGE_MOMENTS: return (const void*)k_moments;
     case STAGE_FINALIZE: return (const void*)k_finalize;
-    case STAGE_HIST: return (const void*)k_hist<KMAX, false>;
+    case STAGE_HIST: return (const void*)k_hist<KMAX, 0>;
     case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS>;
     case STAGE_LOCAL: return (const void*)k_local<PW>;
     default: return (const void*)k_local_hard<PW>;
@@ -1710,10 +1751,12 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_HIST:
-      if (ws.lm.ids)
-        hipLaunchKernelGGL((k_hist<KMAX, true>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      if (ws.lm.ids && ws.lm.direct)
+        hipLaunchKernelGGL((k_hist<KMAX, 2>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      else if (ws.lm.ids)
+        hipLaunchKernelGGL((k_hist<KMAX, 1>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       else
-        hipLaunchKernelGGL((k_hist<KMAX, false>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+        hipLaunchKernelGGL((k_hist<KMAX, 0>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_SCATTER:
       hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(grid), dim3(kBlock), 0, st, ws,
@@ -1740,6 +1783,11 @@ hipError_t launch_reset(const Ws& ws, hipStream_t st) {
 
 hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_init_single, dim3(64), dim3(kBlock), 0, st, ws, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_lists(const Ws& ws, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_lists, dim3(1), dim3(64), 0, st, ws, slot);
   return hipGetLastError();
 }
 

@@ -215,6 +215,10 @@ __global__ void k_ladam_reset(double* __restrict__ adam, LRes* res) {
     res->ticket = 0;
     res->steps_done = 0;
     res->loss_first = res->loss_last = 0.0;
+    res->fail = 0;
+    res->maxc = 0;
+    res->trained = 0;
+    res->smax_init = res->smax_trained = 0;
   }
 }
 
@@ -626,10 +630,7 @@ __global__ void __launch_bounds__(kBlock) k_lcheck(const uint64_t* __restrict__ 
   if (my_bad) atomicOr(&bad, 1u);
   atomicMax(&maxc, (unsigned long long)mc);
   __syncthreads();
-  if (t == 0) {
-    res->fail = bad;
-    res->maxc = maxc;
-  }
+  if (t == 0) res->fail = bad;
 }
 
 // largest cluster of a first-pass histogram given as exclusive starts
@@ -646,6 +647,27 @@ __global__ void __launch_bounds__(kBlock) k_lmaxcount(const uint32_t* __restrict
   atomicMax(&mx, m);
   __syncthreads();
   if (threadIdx.x == 0) *out = mx;
+}
+
+// cluster sizes of the learned map over all keys, thresholds searched in
+// LDS (counts must start at zero; for the report's counts output)
+__global__ void __launch_bounds__(kBlock) k_lfine_hist(const uint64_t* __restrict__ x, uint64_t n,
+                                                       const uint64_t* __restrict__ thr,
+                                                       const LRes* res, int B,
+                                                       uint32_t* __restrict__ counts) {
+  __shared__ uint64_t t[kKMax];
+  __shared__ uint32_t h[kKMax];
+  const uint32_t nt = min(res->nt, (uint32_t)(B - 1));
+  for (uint32_t q = threadIdx.x; q < nt; q += kBlock) t[q] = thr[q];
+  for (int b = threadIdx.x; b < B; b += kBlock) h[b] = 0;
+  __syncthreads();
+  const uint32_t top = top_pow2(nt);
+  for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock)
+    atomicAdd(&h[thr_cluster(t, nt, top, x[i])], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += kBlock)
+    if (h[b]) atomicAdd(&counts[b], h[b]);
 }
 
 // cluster counts of the first pass (tests): counts[b] from the exclusive starts
@@ -754,6 +776,14 @@ hipError_t launch_lthr_check(const uint64_t* thr, LRes* res, hipStream_t st) {
 
 hipError_t launch_lmaxcount(const uint32_t* bst, uint64_t n, int B, uint64_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_lmaxcount, dim3(1), dim3(kBlock), 0, st, bst, n, B, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lfine_hist(const uint64_t* x, uint64_t n, const uint64_t* thr, const LRes* res,
+                             int B, uint32_t* counts, hipStream_t st) {
+  const int blocks = (int)std::min<uint64_t>((n + kBlock * 16 - 1) / (kBlock * 16), 2048);
+  hipLaunchKernelGGL(k_lfine_hist, dim3(std::max(blocks, 1)), dim3(kBlock), 0, st, x, n, thr, res,
+                     B, counts);
   return hipGetLastError();
 }
 
