@@ -223,8 +223,8 @@ __global__ void k_ladam_reset(double* __restrict__ adam, LRes* res) {
 }
 
 // ---------------------------------------------------------------------------
-// one training step over minibatch j = step mod nb (samples i = j, j + nb, ...)
-// mode 0: Adam step; mode 1: write the batch gradient and loss to gout
+// gradient of one training step over minibatch j = step mod nb (samples
+// i = j, j + nb, ...): each workgroup writes the sums over its 256 samples
 // ---------------------------------------------------------------------------
 constexpr int kTB = 256;          // samples per workgroup
 constexpr int kRow = kTB + 1;     // padded row of the reduction matrix
@@ -233,8 +233,6 @@ constexpr int kPartW = kNP + 1;   // partial record: gradient, then loss
 struct TrainSmem {
   MlpP par;
   float rows[2 * kH + 2][kRow];   // one column per sample of the workgroup
-  double dsum[kWaves];
-  uint32_t last;
 };
 
 constexpr double kBeta1 = 0.9, kBeta2 = 0.999, kAdamEps = 1e-8;
@@ -245,9 +243,9 @@ __device__ __forceinline__ bool is_weight(int i) {
 
 __global__ void __launch_bounds__(kTB) k_ltrain(const double* __restrict__ U,
                                                 const float* __restrict__ Y, uint64_t m,
-                                                uint32_t nb, uint32_t step, MlpP* par,
-                                                double* adam, float* part, LRes* res, double lr,
-                                                int mode, double* gout) {
+                                                uint32_t nb, uint32_t step,
+                                                const MlpP* __restrict__ par,
+                                                float* __restrict__ part) {
   __shared__ TrainSmem sm;
   const int t = threadIdx.x;
   const uint32_t j = step % nb;
@@ -350,67 +348,73 @@ __global__ void __launch_bounds__(kTB) k_ltrain(const double* __restrict__ U,
     out[kW1 + t] = acc;
   }
 
-  // the last workgroup to finish sums the partials in workgroup order
-  __threadfence();
-  __syncthreads();
-  if (t == 0) sm.last = (atomicAdd(&res->ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!sm.last) return;
-  __threadfence();
-  const uint32_t G = gridDim.x;
-  double b1p = 0.0, b2p = 0.0;
-  if (mode == 0) {
-    // running powers beta^(step + 1), by repeated products (bias correction)
-    b1p = 1.0;
-    b2p = 1.0;
-    for (uint32_t s = 0; s <= step; ++s) {
-      b1p = __dmul_rn(b1p, kBeta1);
-      b2p = __dmul_rn(b2p, kBeta2);
-    }
+}
+
+// Sums the partials of the G workgroups of a step in workgroup order (one
+// thread per parameter, binary64), then mode 0: Adam step with projection
+// (b1p, b2p: beta1^(step+1), beta2^(step+1), by repeated products on the
+// host); mode 1: the gradient and the loss into gout.
+__global__ void __launch_bounds__(64) k_lreduce(const float* __restrict__ part, uint32_t G,
+                                                MlpP* par, double* adam, LRes* res, double lr,
+                                                double b1p, double b2p, uint32_t step, int mode,
+                                                double* gout) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= kPartW) return;
+  double g = 0.0;
+  uint32_t b = 0;
+  for (; b + 8 <= G; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(uint64_t)(b + u) * kPartW + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g = __dadd_rn(g, (double)v[u]);
   }
-  for (int i = t; i < kPartW; i += kTB) {
-    double g = 0.0;
-    for (uint32_t b = 0; b < G; ++b) g = __dadd_rn(g, (double)part[(uint64_t)b * kPartW + i]);
-    if (mode == 1) {
-      gout[i] = g;
-      continue;
-    }
-    if (i == kNP) {  // the batch loss
-      if (step == 0 || res->steps_done == 0) res->loss_first = g;
-      res->loss_last = g;
-      continue;
-    }
-    double m1v = adam[i], m2v = adam[kNP + i];
-    m1v = __dadd_rn(__dmul_rn(kBeta1, m1v), __dmul_rn(1.0 - kBeta1, g));
-    m2v = __dadd_rn(__dmul_rn(kBeta2, m2v), __dmul_rn(1.0 - kBeta2, __dmul_rn(g, g)));
-    adam[i] = m1v;
-    adam[kNP + i] = m2v;
-    const double mh = __ddiv_rn(m1v, 1.0 - b1p);
-    const double vh = __ddiv_rn(m2v, 1.0 - b2p);
-    // parameter i: binary64 in the first layer, binary32 after it
-    double* pd = i < kB1 ? &par->w1[i] : (i < kW2 ? &par->b1[i - kB1] : nullptr);
-    float* pf = i < kW2 ? nullptr
-                        : (i < kB2 ? &par->w2[i - kW2]
-                                   : (i < kW3 ? &par->b2[i - kB2]
-                                              : (i < kB3 ? &par->w3[i - kW3] : &par->b3)));
-    const double cur = pd ? *pd : (double)*pf;
-    double pn = __dsub_rn(cur, __ddiv_rn(__dmul_rn(lr, mh), __dadd_rn(sqrt(vh), kAdamEps)));
-    if (is_weight(i) && !(pn > 0.0)) pn = 0.0;   // projection onto W >= 0
-    if (pd) *pd = pn;
-    else *pf = __double2float_rn(pn);
+  for (; b < G; ++b) g = __dadd_rn(g, (double)part[(uint64_t)b * kPartW + i]);
+  if (mode == 1) {
+    gout[i] = g;
+    return;
   }
-  __syncthreads();
-  if (t == 0) {
-    res->ticket = 0;
-    if (mode == 0) res->steps_done = res->steps_done + 1;
+  if (i == kNP) {  // the batch loss (before this step's update)
+    if (step == 0) res->loss_first = g;
+    res->loss_last = g;
+    res->steps_done = res->steps_done + 1;
+    return;
   }
+  double m1v = adam[i], m2v = adam[kNP + i];
+  m1v = __dadd_rn(__dmul_rn(kBeta1, m1v), __dmul_rn(1.0 - kBeta1, g));
+  m2v = __dadd_rn(__dmul_rn(kBeta2, m2v), __dmul_rn(1.0 - kBeta2, __dmul_rn(g, g)));
+  adam[i] = m1v;
+  adam[kNP + i] = m2v;
+  const double mh = __ddiv_rn(m1v, 1.0 - b1p);
+  const double vh = __ddiv_rn(m2v, 1.0 - b2p);
+  // parameter i: binary64 in the first layer, binary32 after it
+  double* pd = i < kB1 ? &par->w1[i] : (i < kW2 ? &par->b1[i - kB1] : nullptr);
+  float* pf = i < kW2 ? nullptr
+                      : (i < kB2 ? &par->w2[i - kW2]
+                                 : (i < kW3 ? &par->b2[i - kB2]
+                                            : (i < kB3 ? &par->w3[i - kW3] : &par->b3)));
+  const double cur = pd ? *pd : (double)*pf;
+  double pn = __dsub_rn(cur, __ddiv_rn(__dmul_rn(lr, mh), __dadd_rn(sqrt(vh), kAdamEps)));
+  if (is_weight(i) && !(pn > 0.0)) pn = 0.0;   // projection onto W >= 0
+  if (pd) *pd = pn;
+  else *pf = __double2float_rn(pn);
 }
 
 // ---------------------------------------------------------------------------
-// thresholds: t_b = min{x : cluster(x) >= b}, b = 1..nt, nt = cluster(2^64 - 1);
-// bisection over [0, 2^64 - 1] halves an interval of 2^64 keys, so every
-// lane runs exactly 64 rounds
+// thresholds: t_b = min{x : cluster(x) >= b}, b = 1..nt, nt = cluster(2^64 - 1).
+// A 17-way search: 16 lanes evaluate 16 points that cut [lo, hi] into 17
+// parts, the first point whose cluster is >= b bounds the next interval;
+// about 16 rounds instead of 64 bisection steps.  For a non-decreasing map
+// the least such key is unique, so any exact search finds the same t_b.
 // ---------------------------------------------------------------------------
+constexpr int kTLanes = 16;
+
+__device__ __forceinline__ uint64_t tpoint(uint64_t lo, uint64_t d, uint32_t j) {
+  // lo + floor(d * j / 17) without 128-bit arithmetic (j <= 16)
+  const uint64_t q = d / 17, r = d % 17;
+  return lo + q * j + (r * j) / 17;
+}
+
 __global__ void __launch_bounds__(256) k_lthresh(const MlpP* __restrict__ par, int B, LRes* res,
                                                  uint64_t* __restrict__ thr) {
   __shared__ MlpP sp;
@@ -419,18 +423,33 @@ __global__ void __launch_bounds__(256) k_lthresh(const MlpP* __restrict__ par, i
   const uint64_t smin = res->smin, smax = res->smax;
   const uint32_t nt = mlp_cluster(sp, ~0ull, smin, smax, B);
   if (blockIdx.x == 0 && threadIdx.x == 0) res->nt = nt;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x + 1; b < (uint32_t)B;
-       b += gridDim.x * blockDim.x) {
-    uint64_t v = 0;
-    if (b <= nt) {
-      uint64_t lo = 0, hi = ~0ull;
-      while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (mlp_cluster(sp, mid, smin, smax, B) >= b) hi = mid; else lo = mid + 1;
+  const uint32_t ln = threadIdx.x & (kWave - 1);
+  const uint32_t grp = ln / kTLanes, j = ln % kTLanes + 1;   // point j of 1..16
+  const uint32_t per_wave = kWave / kTLanes;
+  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+  for (uint32_t base = wid * per_wave; base < (uint32_t)B - 1; base += nwaves * per_wave) {
+    const uint32_t b = base + grp + 1;            // this group's threshold
+    bool active = b <= nt;
+    uint64_t lo = 0, hi = ~0ull;                  // the answer lies in [lo, hi]
+    while (__ballot(active)) {
+      const uint64_t d = hi - lo;
+      const uint64_t p = tpoint(lo, d, j);
+      const bool pred = active && mlp_cluster(sp, p, smin, smax, B) >= b;
+      const uint32_t mask = (uint32_t)(__ballot(pred) >> (grp * kTLanes)) & 0xFFFFu;
+      if (active) {
+        if (mask) {
+          const uint32_t js = __ffs(mask);        // first point (1-based) with cluster >= b
+          const uint64_t nhi = tpoint(lo, d, js);
+          if (js > 1) lo = tpoint(lo, d, js - 1) + 1;
+          hi = nhi;
+        } else {
+          lo = tpoint(lo, d, kTLanes) + 1;
+        }
+        if (lo >= hi) active = false;
       }
-      v = lo;
     }
-    thr[b - 1] = v;
+    if (j == 1 && b < (uint32_t)B) thr[b - 1] = b <= nt ? lo : 0;
   }
 }
 
@@ -725,13 +744,20 @@ hipError_t launch_ltrain(const double* U, const float* Y, uint64_t m, uint32_t n
   const uint32_t j = step % nb;
   const uint64_t cnt = m > j ? (m - j + nb - 1) / nb : 0;
   const uint32_t G = (uint32_t)std::max<uint64_t>(1, (cnt + kTB - 1) / kTB);
-  hipLaunchKernelGGL(k_ltrain, dim3(G), dim3(kTB), 0, st, U, Y, m, nb, step, par, adam, part, res,
-                     lr, mode, gout);
+  hipLaunchKernelGGL(k_ltrain, dim3(G), dim3(kTB), 0, st, U, Y, m, nb, step, (const MlpP*)par,
+                     part);
+  double b1p = 1.0, b2p = 1.0;   // beta^(step + 1) by repeated products
+  for (uint32_t s = 0; s <= step && mode == 0; ++s) {
+    b1p = b1p * kBeta1;
+    b2p = b2p * kBeta2;
+  }
+  hipLaunchKernelGGL(k_lreduce, dim3((kPartW + 63) / 64), dim3(64), 0, st, (const float*)part, G,
+                     par, adam, res, lr, b1p, b2p, step, mode, gout);
   return hipGetLastError();
 }
 
 hipError_t launch_lthresh(const MlpP* par, int B, LRes* res, uint64_t* thr, hipStream_t st) {
-  const int blocks = (B - 1 + 255) / 256;
+  const int blocks = ((B - 1) * kTLanes + 255) / 256;
   hipLaunchKernelGGL(k_lthresh, dim3(std::max(blocks, 1)), dim3(256), 0, st, par, B, res, thr);
   return hipGetLastError();
 }
