@@ -236,6 +236,7 @@ def run_learned(steps, warmup, dev, n=10**8):
     ms_fit, reps = timed(None)
     ms_reuse, reps2 = timed(reuse)
     st = zs.zsort_get_last_stats()
+    ms_512, reps3 = timed(dict(reuse, buckets=512))
     log(f"[bench] learned: {ms_fit:.3f} ms/step fitted per call, {ms_reuse:.3f} reused; imbalance "
         f"{diag['imbalance_learned']:.2f} vs z-score {diag['imbalance_zscore']:.1f}")
     return {"workload": f"{n} u64 keys, 4-component mixture (narrow heavy component mid-range), "
@@ -244,16 +245,18 @@ def run_learned(steps, warmup, dev, n=10**8):
             "ms_per_step": round(ms_fit, 4), "gkeys_per_s": round(n / ms_fit / 1e6, 3),
             "ms_per_step_model_reused": round(ms_reuse, 4),
             "gkeys_per_s_model_reused": round(n / ms_reuse / 1e6, 3),
+            "ms_per_step_model_reused_512_clusters": round(ms_512, 4),
+            "gkeys_per_s_model_reused_512_clusters": round(n / ms_512 / 1e6, 3),
             "fit_ms": round(sum(r["train_ms"] for r in reps) / len(reps), 4),
             "first_pass_ms": round(sum(r["first_pass_ms"] for r in reps2) / len(reps2), 4),
             "imbalance_learned": round(diag["imbalance_learned"], 3),
             "imbalance_zscore": round(diag["imbalance_zscore"], 3),
-            "used_learned": sum(r["used_learned"] for r in reps + reps2),
-            "fallbacks": sum(r["fallback"] for r in reps + reps2),
+            "used_learned": sum(r["used_learned"] for r in reps + reps2 + reps3),
+            "fallbacks": sum(r["fallback"] for r in reps + reps2 + reps3),
             "trained_kept": sum(r["trained"] for r in reps),
             "sample_max_cluster_init_vs_trained": [reps[0]["sample_max_init"],
                                                    reps[0]["sample_max_trained"]],
-            "levels": st["levels"], "calls": len(reps) + len(reps2)}
+            "levels": st["levels"], "calls": len(reps) + len(reps2) + len(reps3)}
 
 
 def roofline(kt, stats, pw, steps, traffic_file, cfg):
