@@ -1027,8 +1027,9 @@ struct ScatSmem {
   uint16_t cnt[kWaves][KMAX];   // per-wave counts -> per-wave exclusive prefix (<= T)
   uint32_t tst[KMAX];           // tile exclusive starts
   uint32_t gbase[KMAX];         // running destination of each cluster (n < 2^31)
-  uint64_t stage[T];            // keys in cluster order, then the payloads
-  uint16_t sbk[T];
+  uint64_t stage[T];            // keys in cluster order (then 8-byte payloads)
+  uint32_t sdst[T];             // destination of each staged element (~0u: none)
+  uint32_t spay4[PW == 4 ? T : 1];  // 4-byte payloads, staged with their keys
   uint32_t sh[kWaves + 2];
 };
 
@@ -1075,21 +1076,32 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
       if (stp) base += stp[b] & kValMask;
       sm.gbase[b] = (uint32_t)base;
     }
-    for (uint64_t tb = beg; tb < end; tb += T) {
-      const uint32_t tn = (uint32_t)min((uint64_t)T, end - tb);
-      for (int b = ln; b < k; b += kWave) sm.cnt[wv][b] = 0;
-      __syncthreads();
-      uint64_t key[ROUNDS];
-      P pay[ROUNDS];
-      uint32_t bk[ROUNDS], rk[ROUNDS];
+    // Tiles of T keys.  (Loading the next tile while the current one is
+    // staged and written costs registers and occupancy; with kPrefetch off
+    // each tile loads at its start.)
+    constexpr bool kPrefetch = false;
+    uint64_t key[ROUNDS];
+    P pay[ROUNDS];
+    uint32_t bk[ROUNDS];
+    auto load_tile = [&](uint64_t t0, uint64_t (&kk)[ROUNDS], P (&pp)[ROUNDS],
+                         uint32_t (&ll)[ROUNDS]) {
+      const uint32_t n0 = t0 < end ? (uint32_t)min((uint64_t)T, end - t0) : 0u;
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
-        const bool valid = i < tn;
-        key[r] = valid ? xin[tb + i] : 0ull;
-        pay[r] = valid ? pay_load<PW>(pin, tb + i) : (P)0;
-        bk[r] = (lmap && valid) ? (uint32_t)ws.lm.ids[tb + i] : 0u;  // learned map: ids of hist
+        const bool valid = i < n0;
+        kk[r] = valid ? xin[t0 + i] : 0ull;
+        pp[r] = valid ? pay_load<PW>(pin, t0 + i) : (P)0;
+        ll[r] = (lmap && valid) ? (uint32_t)ws.lm.ids[t0 + i] : 0u;  // learned map: ids of hist
       }
+    };
+    if constexpr (kPrefetch) load_tile(beg, key, pay, bk);
+    const uint64_t seg_end = sg.start + sg.count;
+    for (uint64_t tb = beg; tb < end; tb += T) {
+      const uint32_t tn = (uint32_t)min((uint64_t)T, end - tb);
+      // this wave's counters (only this wave touches its row until the barrier)
+      for (int b = ln; b < k; b += kWave) sm.cnt[wv][b] = 0;
+      if constexpr (!kPrefetch) load_tile(tb, key, pay, bk);
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
@@ -1101,9 +1113,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         uint32_t base = 0;
         if (valid) base = sm.cnt[wv][b];
         if (valid && before == 0) sm.cnt[wv][b] = (uint16_t)(base + (uint32_t)__popcll(m));
-        bk[r] = b;
-        rk[r] = base + before;
+        bk[r] = ((base + before) << 12) | b;   // rank within this wave's run (< 2^20), cluster
       }
+      uint64_t nkey[ROUNDS];
+      P npay[ROUNDS];
+      uint32_t nlid[ROUNDS];
+      if constexpr (kPrefetch) load_tile(tb + T, nkey, npay, nlid);
       __syncthreads();
       // per cluster: exclusive prefix over waves, tile count
       for (int b = t; b < k; b += kBlock) {
@@ -1118,32 +1133,39 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
       }
       __syncthreads();
       block_scan_lds(sm.tst, k, sm.sh);
-      // stage the keys in cluster order, write them, then the same for payloads
+      // stage the keys in cluster order with their destinations, write them,
+      // then the same for the payloads
       uint32_t posr[ROUNDS];
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
         posr[r] = 0;
         if (i < tn) {
-          const uint32_t b = bk[r];
-          const uint32_t pos = min(sm.tst[b] + sm.cnt[wv][b] + rk[r], (uint32_t)T - 1);
+          const uint32_t b = bk[r] & 0xFFFu;
+          const uint32_t within = sm.cnt[wv][b] + (bk[r] >> 12);   // rank inside the cluster's run
+          const uint32_t pos = min(sm.tst[b] + within, (uint32_t)T - 1);
+          const uint64_t dst = (uint64_t)sm.gbase[b] + within;
           posr[r] = pos;
           sm.stage[pos] = key[r];
-          sm.sbk[pos] = (uint16_t)b;
+          if constexpr (PW == 4) sm.spay4[pos] = (uint32_t)pay[r];
+          // never outside the segment when the counts are right
+          const bool ok = dst >= sg.start && dst < seg_end;
+          if (!ok) atomicOr(&c->error, ERR_SCATTER);
+          sm.sdst[pos] = ok ? (uint32_t)dst : ~0u;
         }
       }
       __syncthreads();
-      const uint64_t seg_end = sg.start + sg.count;
+      // every destination lies inside the segment (an unset or rejected
+      // entry, ~0u, never does), so a write can never leave the array
+      const uint32_t dend = (uint32_t)seg_end;
       for (uint32_t p = t; p < tn; p += kBlock) {
-        const uint32_t b = sm.sbk[p];
-        const uint64_t dst = (uint64_t)sm.gbase[b] + (p - sm.tst[b]);
-        if (dst < sg.start || dst >= seg_end) {  // never taken when the counts are right
-          atomicOr(&c->error, ERR_SCATTER);
-          continue;
+        const uint32_t d = sm.sdst[p];
+        if (d < dend) {
+          xout[d] = sm.stage[p];
+          if constexpr (PW == 4) reinterpret_cast<uint32_t*>(pout)[d] = sm.spay4[p];
         }
-        xout[dst] = sm.stage[p];
       }
-      if constexpr (PW != 0) {
+      if constexpr (PW == 8) {   // 8-byte payloads: second round through the key stage
         using P2 = typename PayT<PW>::T;
         P2* spay = reinterpret_cast<P2*>(sm.stage);
         __syncthreads();
@@ -1154,10 +1176,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         }
         __syncthreads();
         for (uint32_t p = t; p < tn; p += kBlock) {
-          const uint32_t b = sm.sbk[p];
-          const uint64_t dst = (uint64_t)sm.gbase[b] + (p - sm.tst[b]);
-          if (dst < sg.start || dst >= seg_end) continue;
-          pay_store<PW>(pout, dst, spay[p]);
+          const uint32_t d = sm.sdst[p];
+          if (d < dend) pay_store<PW>(pout, d, spay[p]);
         }
       }
       __syncthreads();
@@ -1167,6 +1187,14 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         sm.gbase[b] += nxt - sm.tst[b];
       }
       __syncthreads();
+      if constexpr (kPrefetch) {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+          key[r] = nkey[r];
+          pay[r] = npay[r];
+          bk[r] = nlid[r];
+        }
+      }
     }
   }
 }
