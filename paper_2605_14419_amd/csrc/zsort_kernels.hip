@@ -1512,25 +1512,40 @@ __device__ __forceinline__ uint32_t c16_get(const uint32_t* c, uint32_t b) {
   return (c[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
 }
 
-template <int PW, int TW, int R>
-__device__ bool fast_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt, uint64_t* rmin,
-                          uint64_t* rmax, uint32_t* sh, const uint64_t* __restrict__ src,
-                          const void* psrc, uint64_t* __restrict__ dst, void* pdst,
-                          uint64_t start, uint32_t n, uint32_t tid) {
-  using P = typename PayT<PW>::T;
-  constexpr uint32_t TT = TW * kWave;  // n <= TT * R
-  const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
-  uint64_t key[R];
-  uint64_t mn = ~0ull, mx = 0;
+// a team's group into registers: key i = r * TT + tid of the group
+template <int PW, int TT, int R>
+__device__ __forceinline__ void group_load(const uint64_t* __restrict__ src, const void* psrc,
+                                           uint64_t start, uint32_t n, uint32_t tid,
+                                           uint64_t (&key)[R], typename PayT<PW>::T (&pay)[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t i = r * TT + tid;
     const bool valid = i < n;
     key[r] = valid ? src[start + i] : 0ull;
-    if (valid) {
+    pay[r] = (PW != 0 && valid) ? pay_load<PW>(psrc, start + i) : (typename PayT<PW>::T)0;
+  }
+}
+
+// Sorts a group held in registers (see group_load); returns false when the
+// bucket pass cannot take it (range above 51 bits, or a bucket above
+// kBucketMax keys) -- the group is then left to the fallback sort.
+template <int PW, int TW, int R>
+__device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt,
+                               uint64_t* rmin, uint64_t* rmax, uint32_t* sh,
+                               const uint64_t* __restrict__ src, const void* psrc,
+                               uint64_t* __restrict__ dst, void* pdst, uint64_t start, uint32_t n,
+                               uint32_t tid, const uint64_t (&key)[R],
+                               const typename PayT<PW>::T (&pay)[R]) {
+  constexpr uint32_t TT = TW * kWave;  // n <= TT * R
+  const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
+  uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * TT + tid;
+    if (i < n) {
       mn = key[r] < mn ? key[r] : mn;
       mx = key[r] > mx ? key[r] : mx;
-      if constexpr (PW != 0) pb[i] = pay_load<PW>(psrc, start + i);
+      if constexpr (PW != 0) pb[i] = pay[r];
     }
   }
 #pragma unroll
@@ -1669,6 +1684,18 @@ __device__ bool fast_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt,
   return true;
 }
 
+template <int PW, int TW, int R>
+__device__ bool fast_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt, uint64_t* rmin,
+                          uint64_t* rmax, uint32_t* sh, const uint64_t* __restrict__ src,
+                          const void* psrc, uint64_t* __restrict__ dst, void* pdst,
+                          uint64_t start, uint32_t n, uint32_t tid) {
+  uint64_t key[R];
+  typename PayT<PW>::T pay[R];
+  group_load<PW, TW * kWave, R>(src, psrc, start, n, tid, key, pay);
+  return fast_sort_regs<PW, TW, R>(kb, pb, cnt, rmin, rmax, sh, src, psrc, dst, pdst, start, n, tid,
+                                   key, pay);
+}
+
 __device__ void push_hard(Ws& ws, int S, const Leaf& lf) {
   const uint32_t h = atomicAdd(&ws.ctl->nhard[S], 1u);
   if (h < ws.leaf_cap) ws.hard[S][h] = lf;
@@ -1719,27 +1746,48 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   uint64_t* kb = sm.k + wv * kWaveCap;
   typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
   uint32_t* cb = sm.cnt + wv * (kWaveCap / 2);
-  for (uint32_t g = blockIdx.x * kWaves + wv; g < nlw; g += gridDim.x * kWaves) {
-    const Leaf lf = ws.leavesw[S][g];
+  // the next group's keys and payloads are loaded while this one is sorted
+  constexpr int RW = kWaveCap / kWave;
+  using P = typename PayT<PW>::T;
+  const uint32_t gs = gridDim.x * kWaves;
+  uint32_t g = blockIdx.x * kWaves + wv;
+  Leaf lf{};
+  uint64_t key[RW];
+  P pay[RW];
+  if (g < nlw) {
+    lf = ws.leavesw[S][g];
+    group_load<PW, kWave, RW>(ws.keys[lf.src], ws.pay[lf.src], lf.start, lf.count, ln, key, pay);
+  }
+  for (; g < nlw; g += gs) {
+    const uint32_t gn = g + gs;
+    Leaf nf{};
+    uint64_t nkey[RW];
+    P npay[RW];
+    if (gn < nlw) {
+      nf = ws.leavesw[S][gn];
+      group_load<PW, kWave, RW>(ws.keys[nf.src], ws.pay[nf.src], nf.start, nf.count, ln, nkey,
+                                npay);
+    }
     const uint64_t* __restrict__ src = ws.keys[lf.src];
     const void* psrc = ws.pay[lf.src];
     const uint32_t n = lf.count;
     if (ln == 0 && (lf.src != 0 || n > 1)) moved += n;
     if (n <= 1) {
       if (lf.src != 0 && ln == 0 && n == 1) {
-        dst[lf.start] = src[lf.start];
-        if constexpr (PW != 0) pay_store<PW>(pdst, lf.start, pay_load<PW>(psrc, lf.start));
+        dst[lf.start] = key[0];
+        if constexpr (PW != 0) pay_store<PW>(pdst, lf.start, pay[0]);
       }
-      continue;
+    } else {
+      const bool ok = fast_sort_regs<PW, 1, RW>(kb, pb, cb, nullptr, nullptr, nullptr, src, psrc,
+                                                dst, pdst, lf.start, n, ln, key, pay);
+      if (!ok && ln == 0) push_hard(ws, S, lf);
     }
-    bool ok;
-    if (n <= 4 * kWave)
-      ok = fast_sort<PW, 1, 4>(kb, pb, cb, nullptr, nullptr, nullptr, src, psrc, dst, pdst,
-                               lf.start, n, ln);
-    else
-      ok = fast_sort<PW, 1, kWaveCap / kWave>(kb, pb, cb, nullptr, nullptr, nullptr, src, psrc,
-                                              dst, pdst, lf.start, n, ln);
-    if (!ok && ln == 0) push_hard(ws, S, lf);
+    lf = nf;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      key[r] = nkey[r];
+      pay[r] = npay[r];
+    }
   }
   // one statistics atomic per workgroup
 #pragma unroll
