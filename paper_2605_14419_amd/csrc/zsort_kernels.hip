@@ -1030,11 +1030,10 @@ struct ScatSmem {
   uint64_t stage[T];            // keys in cluster order (then 8-byte payloads)
   uint32_t sdst[T];             // destination of each staged element (~0u: none)
   uint32_t spay4[PW == 4 ? T : 1];  // 4-byte payloads, staged with their keys
-  uint32_t sh[kWaves + 2];
 };
 
 template <int KMAX, int KBITS, int PW, int ROUNDS>
-__global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
+__global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, int L) {
   using P = typename PayT<PW>::T;
   using Sm = ScatSmem<KMAX, PW, ROUNDS>;
   constexpr int T = Sm::T;
@@ -1045,7 +1044,10 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
   const int k = ws.p.k;
   const uint64_t ch = (uint64_t)ws.p.chunk;
-  const uint64_t* __restrict__ xin = ws.keys[S];
+  // (no __restrict__ on the inputs: a restrict-qualified read-only pointer
+  // lets the compiler re-load a tile's keys from memory in the staging phase
+  // instead of keeping them in registers)
+  const uint64_t* xin = ws.keys[S];
   uint64_t* __restrict__ xout = ws.keys[N];
   const void* pin = ws.pay[S];
   void* pout = ws.pay[N];
@@ -1096,19 +1098,42 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
       }
     };
     if constexpr (kPrefetch) load_tile(beg, key, pay, bk);
+    // segment bounds in registers (a reference into global memory would be
+    // re-read after every store the compiler cannot prove apart from it)
+    const uint64_t seg_start = sg.start;
     const uint64_t seg_end = sg.start + sg.count;
+    // Peers (lanes of a wave with the same cluster) by one LDS OR per key
+    // into a per-wave mask slot of the cluster, read back and cleared --
+    // OR is order-free, so the mask is exact; the slots live in the key
+    // stage, unused until staging.  Without room for them: one ballot per
+    // cluster-index bit.
+    constexpr bool kPeerLds = kWaves * KMAX <= T;
+    uint64_t* const peer = reinterpret_cast<uint64_t*>(sm.stage) + (kPeerLds ? wv * KMAX : 0);
     for (uint64_t tb = beg; tb < end; tb += T) {
       const uint32_t tn = (uint32_t)min((uint64_t)T, end - tb);
-      // this wave's counters (only this wave touches its row until the barrier)
-      for (int b = ln; b < k; b += kWave) sm.cnt[wv][b] = 0;
+      // this wave's counters and peer slots (only this wave touches them
+      // until the barrier)
+      for (int b = ln; b < k; b += kWave) {
+        sm.cnt[wv][b] = 0;
+        if constexpr (kPeerLds) peer[b] = 0ull;
+      }
       if constexpr (!kPrefetch) load_tile(tb, key, pay, bk);
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
         const bool valid = i < tn;
         const uint32_t b = valid ? (lmap ? bk[r] : bucket_of(key[r], mp)) : 0u;
-        const uint64_t act = __ballot(valid);
-        const uint64_t m = match_digit<KBITS>(b, act);
+        uint64_t m;
+        if constexpr (kPeerLds) {
+          if (valid) atomicOr((unsigned long long*)&peer[b], 1ull << ln);
+          __builtin_amdgcn_wave_barrier();
+          m = valid ? peer[b] : 0ull;
+          __builtin_amdgcn_wave_barrier();
+          if (valid) peer[b] = 0ull;
+          __builtin_amdgcn_wave_barrier();
+        } else {
+          m = match_digit<KBITS>(b, __ballot(valid));
+        }
         const uint32_t before = below(m);
         uint32_t base = 0;
         if (valid) base = sm.cnt[wv][b];
@@ -1132,7 +1157,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
         sm.tst[b] = run;
       }
       __syncthreads();
-      block_scan_lds(sm.tst, k, sm.sh);
+      // (the scan's scratch lives in the key stage, which is free until staging)
+      block_scan_lds(sm.tst, k, reinterpret_cast<uint32_t*>(sm.stage));
       // stage the keys in cluster order with their destinations, write them,
       // then the same for the payloads
       uint32_t posr[ROUNDS];
@@ -1149,7 +1175,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Ws ws, int L) {
           sm.stage[pos] = key[r];
           if constexpr (PW == 4) sm.spay4[pos] = (uint32_t)pay[r];
           // never outside the segment when the counts are right
-          const bool ok = dst >= sg.start && dst < seg_end;
+          const bool ok = dst >= seg_start && dst < seg_end;
           if (!ok) atomicOr(&c->error, ERR_SCATTER);
           sm.sdst[pos] = ok ? (uint32_t)dst : ~0u;
         }
