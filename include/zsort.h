@@ -62,8 +62,9 @@ enum {
  *                map, 0..16 (0 = range map everywhere).  Default 8.
  *   chunk        keys per work item of a pass, a multiple of 2048 in
  *                [2048, 2^20] (and of tile).  Default 16384.
- *   tile         keys a workgroup stages through LDS per step of the stable
- *                scatter: 2048 or 4096 (4096 needs k <= 1024).  Default 2048.
+ *   tile         keys a workgroup ranks per step of the stable scatter:
+ *                2048, 4096 (256 threads) or 8192 (1024 threads); above 2048
+ *                needs k <= 1024 and chunk a multiple of tile.  Default 2048.
  *   flags        ZSORT_FLAG_GRAPH: run the whole sort as one cached hipGraph
  *                (every level of the recursion is launched; kernels of empty
  *                levels exit at once).  The graph is captured on a private
@@ -88,11 +89,12 @@ typedef struct zsort_config {
 int zsort_default_config(zsort_config* cfg);
 
 /*
- * Autotuner: times candidate configurations (k in {256, 512, 1024}, tile in
- * {2048, 4096} with chunk 16384 / 32768, cutoff in {1024, 2048}) on a scratch
- * copy of keys/payload (device buffers, left unchanged; seg_offsets may be
- * NULL for a single array) and remembers the fastest for the shape class
- * (n rounded up to a power of two, payload width, single or segmented).
+ * Autotuner: times candidate configurations (k in {256, 512, 1024}; (tile,
+ * chunk) in {(2048, 16384), (4096, 32768), (8192, 8192), (8192, 32768)};
+ * cutoff in {1024, 2048}) on a scratch copy of keys/payload (device buffers,
+ * left unchanged; seg_offsets may be NULL for a single array) and remembers
+ * the fastest for the shape class (n rounded up to a power of two, payload
+ * width, single or segmented).
  * Later calls of that class with cfg == NULL use it.  If the class is already
  * known no timing is done.  cache_path (may be NULL) names a text file of
  * tuned entries that is read first and rewritten afterwards.  best (host, may

@@ -222,8 +222,8 @@ int check_cfg(const zsort_config* c) {
   if (c->cutoff < 1 || c->cutoff > zs::kBlockCap) return ZSORT_EINVAL;
   if (c->max_zlevels < 0 || c->max_zlevels > 16) return ZSORT_EINVAL;
   if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
-  if (c->tile != 2048 && c->tile != 4096) return ZSORT_EINVAL;
-  if (c->tile == 4096 && (c->k > 1024 || c->chunk % 4096)) return ZSORT_EINVAL;
+  if (c->tile != 2048 && c->tile != 4096 && c->tile != 8192) return ZSORT_EINVAL;
+  if (c->tile > 2048 && (c->k > 1024 || c->chunk % c->tile)) return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 
@@ -330,7 +330,8 @@ int grid_size(int k, int pw, int tile, int stage) {
   static std::mutex mu;
   static std::unordered_map<int, int> cache;
   const int kc = k <= 256 ? 0 : (k <= 512 ? 1 : (k <= 1024 ? 2 : 3));
-  const int key = kc | (pw << 2) | ((tile == 4096) << 6) | (stage << 8);
+  const int tc = tile == 8192 ? 2 : (tile == 4096 ? 1 : 0);
+  const int key = kc | (pw << 2) | (tc << 6) | (stage << 8);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   int per = 0;
@@ -878,16 +879,19 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
   zsort_default_config(&win);
   float win_ms = 1e30f;
   const int ks[3] = {256, 512, 1024};
-  const int tiles[2] = {2048, 4096};
+  // (tile, chunk): one-tile work items put the runs of neighbouring tiles
+  // side by side in memory at the same time; larger ones cost the histogram
+  // pass less
+  const int tiles[4][2] = {{2048, 16384}, {4096, 32768}, {8192, 8192}, {8192, 32768}};
   const int cuts[2] = {1024, 2048};
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+    for (int b = 0; b < 4 && e == hipSuccess; ++b)
       for (int d = 0; d < 2 && e == hipSuccess; ++d) {
         zsort_config c;
         zsort_default_config(&c);
         c.k = ks[a];
-        c.tile = tiles[b];
-        c.chunk = tiles[b] == 4096 ? 32768 : 16384;
+        c.tile = tiles[b][0];
+        c.chunk = tiles[b][1];
         c.cutoff = cuts[d];
         float t_best = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
@@ -1178,7 +1182,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
     wz.p.lb = floor_log2(k2);
     Call cz = call;
     cz.cfg.k = k2;
-    if (cz.cfg.tile == 4096 && k2 > 1024) cz.cfg.tile = wz.p.tile = 2048;
+    if (cz.cfg.tile > 2048 && k2 > 1024) cz.cfg.tile = wz.p.tile = 2048;
     // 4b. local sort of the first pass's small clusters; with two stages the
     //     second learned pass (its lists start empty: no moments pass runs
     //     for learned segments); then the z-score levels on what is left

@@ -60,14 +60,16 @@ __device__ __forceinline__ int wave_incl_max(int v) {
   return v;
 }
 
-// exclusive block sum of one value per thread; `sh` holds kWaves words
+// exclusive block sum of one value per thread (NT threads); `sh` holds
+// NT / kWave words
+template <int NT = kBlock>
 __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* sh, uint32_t* total) {
   uint32_t inc = wave_incl_sum(v);
   if (lane() == kWave - 1) sh[wave()] = inc;
   __syncthreads();
   uint32_t base = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) {
+  for (int i = 0; i < NT / kWave; ++i) {
     uint32_t s = sh[i];
     base += (i < (int)wave()) ? s : 0u;
     tot += s;
@@ -78,8 +80,9 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* sh, uin
 }
 
 // in-place exclusive sum over a[0, N) in LDS; returns the total
+template <int NT = kBlock>
 __device__ uint32_t block_scan_lds(uint32_t* a, int N, uint32_t* sh) {
-  const int ipt = (N + kBlock - 1) / kBlock;
+  const int ipt = (N + NT - 1) / NT;
   const int b0 = threadIdx.x * ipt;
   uint32_t s = 0;
   for (int i = 0; i < ipt; ++i) {
@@ -87,7 +90,7 @@ __device__ uint32_t block_scan_lds(uint32_t* a, int N, uint32_t* sh) {
     if (j < N) s += a[j];
   }
   uint32_t tot;
-  uint32_t base = block_excl_sum(s, sh, &tot);
+  uint32_t base = block_excl_sum<NT>(s, sh, &tot);
   for (int i = 0; i < ipt; ++i) {
     int j = b0 + i;
     if (j < N) {
@@ -1021,22 +1024,36 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
 // ---------------------------------------------------------------------------
 // scatter: stable, key + payload, through an LDS-staged tile
 // ---------------------------------------------------------------------------
-template <int KMAX, int PW, int ROUNDS>
+template <int KMAX, int PW, int ROUNDS, int SB>
 struct ScatSmem {
-  static constexpr int T = kBlock * ROUNDS;
-  uint16_t cnt[kWaves][KMAX];   // per-wave counts -> per-wave exclusive prefix (<= T)
-  uint32_t tst[KMAX];           // tile exclusive starts
+  static constexpr int NWV = SB / kWave;           // waves of the workgroup
+  static constexpr int T = SB * ROUNDS;            // keys per tile (held in registers)
+  static constexpr int kFixed = NWV * KMAX * 2 + KMAX * 8;
+  static constexpr int kPerKey = 12 + (PW == 4 ? 4 : 0);
+  // keys per staging window: the whole tile if it fits in LDS, else halves
+  static constexpr int SW = kFixed + T * kPerKey <= 160 * 1024 ? T : T / 2;
+  uint16_t cnt[NWV][KMAX];      // per-wave counts -> per-wave start of the cluster in the tile
+  uint32_t tst[KMAX];           // tile exclusive starts -> destination minus tile position
   uint32_t gbase[KMAX];         // running destination of each cluster (n < 2^31)
-  uint64_t stage[T];            // keys in cluster order (then 8-byte payloads)
-  uint32_t sdst[T];             // destination of each staged element (~0u: none)
-  uint32_t spay4[PW == 4 ? T : 1];  // 4-byte payloads, staged with their keys
+  uint64_t stage[SW];           // keys in cluster order (then 8-byte payloads)
+  uint32_t sdst[SW];            // destination of each staged element (~0u: none)
+  uint32_t spay4[PW == 4 ? SW : 1];  // 4-byte payloads, staged with their keys
 };
 
-template <int KMAX, int KBITS, int PW, int ROUNDS>
-__global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, int L) {
+// A tile of T keys is ranked in registers; its keys then leave in cluster
+// order through LDS windows of SW keys (the whole tile where it fits), so
+// each cluster's run per tile is T / k keys long.
+template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
+__global__ void __launch_bounds__(SB, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, int L) {
   using P = typename PayT<PW>::T;
-  using Sm = ScatSmem<KMAX, PW, ROUNDS>;
+  using Sm = ScatSmem<KMAX, PW, ROUNDS, SB>;
+  constexpr int NWV = Sm::NWV;
   constexpr int T = Sm::T;
+  constexpr int SW = Sm::SW;
+  constexpr int NWIN = T / SW;
+  static_assert(NWIN * SW == T, "tile must be a whole number of windows");
+  static_assert(T <= 8192, "positions are packed in 13 bits");
+  static_assert(sizeof(Sm) <= 160 * 1024, "LDS of one workgroup");
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
@@ -1073,31 +1090,11 @@ __global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     const uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
     const uint64_t* stp = (ci > 0) ? ws.status + (uint64_t)(sg.status_base + ci - 1) * (uint64_t)k : nullptr;
-    for (int b = t; b < k; b += kBlock) {
+    for (int b = t; b < k; b += SB) {
       uint64_t base = sg.start + gb[b];
       if (stp) base += stp[b] & kValMask;
       sm.gbase[b] = (uint32_t)base;
     }
-    // Tiles of T keys.  (Loading the next tile while the current one is
-    // staged and written costs registers and occupancy; with kPrefetch off
-    // each tile loads at its start.)
-    constexpr bool kPrefetch = false;
-    uint64_t key[ROUNDS];
-    P pay[ROUNDS];
-    uint32_t bk[ROUNDS];
-    auto load_tile = [&](uint64_t t0, uint64_t (&kk)[ROUNDS], P (&pp)[ROUNDS],
-                         uint32_t (&ll)[ROUNDS]) {
-      const uint32_t n0 = t0 < end ? (uint32_t)min((uint64_t)T, end - t0) : 0u;
-#pragma unroll
-      for (int r = 0; r < ROUNDS; ++r) {
-        const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
-        const bool valid = i < n0;
-        kk[r] = valid ? xin[t0 + i] : 0ull;
-        pp[r] = valid ? pay_load<PW>(pin, t0 + i) : (P)0;
-        ll[r] = (lmap && valid) ? (uint32_t)ws.lm.ids[t0 + i] : 0u;  // learned map: ids of hist
-      }
-    };
-    if constexpr (kPrefetch) load_tile(beg, key, pay, bk);
     // segment bounds in registers (a reference into global memory would be
     // re-read after every store the compiler cannot prove apart from it)
     const uint64_t seg_start = sg.start;
@@ -1107,7 +1104,7 @@ __global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws
     // OR is order-free, so the mask is exact; the slots live in the key
     // stage, unused until staging.  Without room for them: one ballot per
     // cluster-index bit.
-    constexpr bool kPeerLds = kWaves * KMAX <= T;
+    constexpr bool kPeerLds = NWV * KMAX <= SW;
     uint64_t* const peer = reinterpret_cast<uint64_t*>(sm.stage) + (kPeerLds ? wv * KMAX : 0);
     for (uint64_t tb = beg; tb < end; tb += T) {
       const uint32_t tn = (uint32_t)min((uint64_t)T, end - tb);
@@ -1117,7 +1114,17 @@ __global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws
         sm.cnt[wv][b] = 0;
         if constexpr (kPeerLds) peer[b] = 0ull;
       }
-      if constexpr (!kPrefetch) load_tile(tb, key, pay, bk);
+      uint64_t key[ROUNDS];
+      P pay[ROUNDS];
+      uint32_t bk[ROUNDS];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
+        const bool valid = i < tn;
+        key[r] = valid ? xin[tb + i] : 0ull;
+        bk[r] = (lmap && valid) ? (uint32_t)ws.lm.ids[tb + i] : 0u;  // learned map: ids of hist
+      }
+      // rank of each key among the wave's keys of its cluster
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
@@ -1138,18 +1145,24 @@ __global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws
         uint32_t base = 0;
         if (valid) base = sm.cnt[wv][b];
         if (valid && before == 0) sm.cnt[wv][b] = (uint16_t)(base + (uint32_t)__popcll(m));
-        bk[r] = ((base + before) << 12) | b;   // rank within this wave's run (< 2^20), cluster
+        bk[r] = ((base + before) << 12) | b;   // rank within this wave's run (< 2^13), cluster
       }
-      uint64_t nkey[ROUNDS];
-      P npay[ROUNDS];
-      uint32_t nlid[ROUNDS];
-      if constexpr (kPrefetch) load_tile(tb + T, nkey, npay, nlid);
+      // the payloads load while the tile's cluster starts are worked out
+      // (not during the ranking, whose registers they would crowd: the
+      // empty asm hides the pointer, so the loads cannot be hoisted)
+      const void* pin_late = pin;
+      asm volatile("" : "+s"(pin_late));
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
+        pay[r] = i < tn ? pay_load<PW>(pin_late, tb + i) : (P)0;
+      }
       __syncthreads();
       // per cluster: exclusive prefix over waves, tile count
-      for (int b = t; b < k; b += kBlock) {
+      for (int b = t; b < k; b += SB) {
         uint32_t run = 0;
 #pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
+        for (int q = 0; q < NWV; ++q) {
           const uint32_t v = sm.cnt[q][b];
           sm.cnt[q][b] = (uint16_t)run;
           run += v;
@@ -1158,69 +1171,89 @@ __global__ void __launch_bounds__(kBlock, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws
       }
       __syncthreads();
       // (the scan's scratch lives in the key stage, which is free until staging)
-      block_scan_lds(sm.tst, k, reinterpret_cast<uint32_t*>(sm.stage));
-      // stage the keys in cluster order with their destinations, write them,
-      // then the same for the payloads
-      uint32_t posr[ROUNDS];
+      block_scan_lds<SB>(sm.tst, k, reinterpret_cast<uint32_t*>(sm.stage));
+      // per cluster: start of each wave's run in the tile, destination minus
+      // tile position, and the running destination advanced past this tile
+      constexpr int KPT = (KMAX + SB - 1) / SB;
+      uint32_t st0[KPT], stn[KPT];
 #pragma unroll
-      for (int r = 0; r < ROUNDS; ++r) {
-        const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
-        posr[r] = 0;
-        if (i < tn) {
-          const uint32_t b = bk[r] & 0xFFFu;
-          const uint32_t within = sm.cnt[wv][b] + (bk[r] >> 12);   // rank inside the cluster's run
-          const uint32_t pos = min(sm.tst[b] + within, (uint32_t)T - 1);
-          const uint64_t dst = (uint64_t)sm.gbase[b] + within;
-          posr[r] = pos;
-          sm.stage[pos] = key[r];
-          if constexpr (PW == 4) sm.spay4[pos] = (uint32_t)pay[r];
-          // never outside the segment when the counts are right
-          const bool ok = dst >= seg_start && dst < seg_end;
-          if (!ok) atomicOr(&c->error, ERR_SCATTER);
-          sm.sdst[pos] = ok ? (uint32_t)dst : ~0u;
+      for (int j = 0; j < KPT; ++j) {
+        const int b = t + j * SB;
+        st0[j] = b < k ? sm.tst[b] : 0u;
+        stn[j] = b + 1 < k ? sm.tst[b + 1] : tn;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const int b = t + j * SB;
+        if (b < k) {
+#pragma unroll
+          for (int q = 0; q < NWV; ++q) sm.cnt[q][b] = (uint16_t)(sm.cnt[q][b] + st0[j]);
+          const uint32_t gbv = sm.gbase[b];
+          sm.tst[b] = gbv - st0[j];
+          sm.gbase[b] = gbv + (stn[j] - st0[j]);
         }
       }
       __syncthreads();
-      // every destination lies inside the segment (an unset or rejected
-      // entry, ~0u, never does), so a write can never leave the array
-      const uint32_t dend = (uint32_t)seg_end;
-      for (uint32_t p = t; p < tn; p += kBlock) {
-        const uint32_t d = sm.sdst[p];
-        if (d < dend) {
-          xout[d] = sm.stage[p];
-          if constexpr (PW == 4) reinterpret_cast<uint32_t*>(pout)[d] = sm.spay4[p];
-        }
+      // position of each key in the tile's cluster order
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t b = bk[r] & 0xFFFu;
+        const uint32_t pos = min((uint32_t)sm.cnt[wv][b] + (bk[r] >> 12), (uint32_t)T - 1);
+        bk[r] = (pos << 12) | b;
       }
-      if constexpr (PW == 8) {   // 8-byte payloads: second round through the key stage
-        using P2 = typename PayT<PW>::T;
-        P2* spay = reinterpret_cast<P2*>(sm.stage);
-        __syncthreads();
+      // window by window: stage the keys with their destinations, write
+      // them, then the same for the payloads
+      const uint32_t dend = (uint32_t)seg_end;
+#pragma unroll 1
+      for (int wi = 0; wi < NWIN; ++wi) {
+        const uint32_t p0 = (uint32_t)(wi * SW);
+        if (p0 >= tn) break;
+        const uint32_t pn = min((uint32_t)SW, tn - p0);
+        if (wi > 0) __syncthreads();   // the previous window has left the stage
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
           const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
-          if (i < tn) spay[posr[r]] = pay[r];
+          const uint32_t q = (bk[r] >> 12) - p0;
+          if (i < tn && q < (uint32_t)SW) {
+            const uint32_t b = bk[r] & 0xFFFu;
+            const uint64_t dst = (uint64_t)(uint32_t)((bk[r] >> 12) + sm.tst[b]);
+            sm.stage[q] = key[r];
+            if constexpr (PW == 4) sm.spay4[q] = (uint32_t)pay[r];
+            // never outside the segment when the counts are right
+            const bool ok = dst >= seg_start && dst < seg_end;
+            if (!ok) atomicOr(&c->error, ERR_SCATTER);
+            sm.sdst[q] = ok ? (uint32_t)dst : ~0u;
+          }
         }
         __syncthreads();
-        for (uint32_t p = t; p < tn; p += kBlock) {
+        // every destination lies inside the segment (an unset or rejected
+        // entry, ~0u, never does), so a write can never leave the array
+        for (uint32_t p = t; p < pn; p += SB) {
           const uint32_t d = sm.sdst[p];
-          if (d < dend) pay_store<PW>(pout, d, spay[p]);
+          if (d < dend) {
+            xout[d] = sm.stage[p];
+            if constexpr (PW == 4) reinterpret_cast<uint32_t*>(pout)[d] = sm.spay4[p];
+          }
         }
-      }
-      __syncthreads();
-      // advance the running destinations by this tile's counts
-      for (int b = t; b < k; b += kBlock) {
-        const uint32_t nxt = (b + 1 < k) ? sm.tst[b + 1] : tn;
-        sm.gbase[b] += nxt - sm.tst[b];
-      }
-      __syncthreads();
-      if constexpr (kPrefetch) {
+        if constexpr (PW == 8) {   // 8-byte payloads: second round through the key stage
+          using P2 = typename PayT<PW>::T;
+          P2* spay = reinterpret_cast<P2*>(sm.stage);
+          __syncthreads();
 #pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-          key[r] = nkey[r];
-          pay[r] = npay[r];
-          bk[r] = nlid[r];
+          for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t i = wv * (kWave * ROUNDS) + r * kWave + ln;
+            const uint32_t q = (bk[r] >> 12) - p0;
+            if (i < tn && q < (uint32_t)SW) spay[q] = pay[r];
+          }
+          __syncthreads();
+          for (uint32_t p = t; p < pn; p += SB) {
+            const uint32_t d = sm.sdst[p];
+            if (d < dend) pay_store<PW>(pout, d, spay[p]);
+          }
         }
       }
+      __syncthreads();
     }
   }
 }
@@ -1831,19 +1864,19 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int KMAX, int KBITS, int PW, int ROUNDS>
+template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
 static const void* stage_fn(int stage) {
   switch (stage) {
     case STAGE_MOMENTS: return (const void*)k_moments;
     case STAGE_FINALIZE: return (const void*)k_finalize;
     case STAGE_HIST: return (const void*)k_hist<KMAX, 0>;
-    case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS>;
+    case STAGE_SCATTER: return (const void*)k_scatter<KMAX, KBITS, PW, ROUNDS, SB>;
     case STAGE_LOCAL: return (const void*)k_local<PW>;
     default: return (const void*)k_local_hard<PW>;
   }
 }
 
-template <int KMAX, int KBITS, int PW, int ROUNDS>
+template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
 static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t st) {
   switch (stage) {
     case STAGE_MOMENTS:
@@ -1861,7 +1894,7 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
         hipLaunchKernelGGL((k_hist<KMAX, 0>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_SCATTER:
-      hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS>), dim3(grid), dim3(kBlock), 0, st, ws,
+      hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS, SB>), dim3(grid), dim3(SB), 0, st, ws,
                          L);
       break;
     case STAGE_LOCAL:
@@ -1906,34 +1939,39 @@ hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, 
   return hipGetLastError();
 }
 
-// (k, payload bytes, tile) -> template instance; KMAX 4096 only with 2048-key tiles
+// (k, payload bytes, tile) -> template instance (clusters, their bits, payload
+// bytes, keys per thread, threads of the scatter's workgroup).  Tiles of 2048
+// and 4096 keys take 256 threads (8 and 16 keys each); 8192-key tiles take
+// 1024 threads of 8 keys: twice the waves per compute unit of the 4096-key
+// tile at the same registers per thread, and twice its run of each cluster
+// per tile.  KMAX 4096 only with 2048-key tiles.
+#define ZS_TILES(CALL, KM, KB, PWV)                                         \
+  do {                                                                      \
+    if (ws_tile == 8192) CALL(KM, KB, PWV, 8, 1024);                        \
+    else if (ws_tile == 4096) CALL(KM, KB, PWV, 16, 256);                   \
+    else CALL(KM, KB, PWV, 8, 256);                                         \
+  } while (0)
+#define ZS_PAYLOADS(CALL, KM, KB)                                           \
+  do {                                                                      \
+    if (pw == 0) ZS_TILES(CALL, KM, KB, 0);                                 \
+    else if (pw == 4) ZS_TILES(CALL, KM, KB, 4);                            \
+    else ZS_TILES(CALL, KM, KB, 8);                                         \
+  } while (0)
 #define ZS_DISPATCH(CALL)                                                   \
   do {                                                                      \
-    const int r16 = ws_tile == 4096;                                        \
-    if (k <= 256) {                                                         \
-      if (pw == 0) { if (r16) CALL(256, 8, 0, 16); else CALL(256, 8, 0, 8); } \
-      else if (pw == 4) { if (r16) CALL(256, 8, 4, 16); else CALL(256, 8, 4, 8); } \
-      else { if (r16) CALL(256, 8, 8, 16); else CALL(256, 8, 8, 8); }       \
-    } else if (k <= 512) {                                                  \
-      if (pw == 0) { if (r16) CALL(512, 9, 0, 16); else CALL(512, 9, 0, 8); } \
-      else if (pw == 4) { if (r16) CALL(512, 9, 4, 16); else CALL(512, 9, 4, 8); } \
-      else { if (r16) CALL(512, 9, 8, 16); else CALL(512, 9, 8, 8); }       \
-    } else if (k <= 1024) {                                                 \
-      if (pw == 0) { if (r16) CALL(1024, 10, 0, 16); else CALL(1024, 10, 0, 8); } \
-      else if (pw == 4) { if (r16) CALL(1024, 10, 4, 16); else CALL(1024, 10, 4, 8); } \
-      else { if (r16) CALL(1024, 10, 8, 16); else CALL(1024, 10, 8, 8); }   \
-    } else {                                                                \
-      if (pw == 0) CALL(4096, 12, 0, 8);                                    \
-      else if (pw == 4) CALL(4096, 12, 4, 8);                               \
-      else CALL(4096, 12, 8, 8);                                            \
-    }                                                                       \
+    if (k <= 256) ZS_PAYLOADS(CALL, 256, 8);                                \
+    else if (k <= 512) ZS_PAYLOADS(CALL, 512, 9);                           \
+    else if (k <= 1024) ZS_PAYLOADS(CALL, 1024, 10);                        \
+    else if (pw == 0) CALL(4096, 12, 0, 8, 256);                            \
+    else if (pw == 4) CALL(4096, 12, 4, 8, 256);                            \
+    else CALL(4096, 12, 8, 8, 256);                                         \
   } while (0)
 
 hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st) {
   const int k = ws.p.k;
   const int pw = ws.p.pw;
   const int ws_tile = ws.p.tile;
-#define ZS_LAUNCH(KM, KB, PWV, R) launch_stage_t<KM, KB, PWV, R>(ws, L, stage, grid, st)
+#define ZS_LAUNCH(KM, KB, PWV, R, SB) launch_stage_t<KM, KB, PWV, R, SB>(ws, L, stage, grid, st)
   ZS_DISPATCH(ZS_LAUNCH);
 #undef ZS_LAUNCH
   return hipGetLastError();
@@ -1942,15 +1980,19 @@ hipError_t launch_stage(const Ws& ws, int L, int stage, int grid, hipStream_t st
 // resident workgroups per compute unit of a stage's kernel (at least 1)
 int stage_blocks_per_cu(int k, int pw, int ws_tile, int stage) {
   const void* fn = nullptr;
-#define ZS_FN(KM, KB, PWV, R) fn = stage_fn<KM, KB, PWV, R>(stage)
+  int threads = kBlock;
+#define ZS_FN(KM, KB, PWV, R, SB) \
+  fn = stage_fn<KM, KB, PWV, R, SB>(stage), threads = stage == STAGE_SCATTER ? SB : kBlock
   ZS_DISPATCH(ZS_FN);
 #undef ZS_FN
   if (!fn) return 1;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess || nb < 1)
     return 1;
   return nb;
 }
 #undef ZS_DISPATCH
+#undef ZS_PAYLOADS
+#undef ZS_TILES
 
 }  // namespace zs

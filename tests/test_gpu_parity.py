@@ -208,3 +208,39 @@ def test_ten_million_vs_oracle(name):
     assert st["device_error"] == 0, st
     ok, oi, _ = oracle.sort(x, idx, k=1024, cutoff=2048, max_zlevels=8)
     assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
+@pytest.mark.parametrize("tile,k,pw", [(t, k, pw) for t in (4096, 8192) for k in (256, 512, 1024)
+                                        for pw in (0, 4, 8)])
+def test_tiles_vs_oracle(tile, k, pw):
+    """tiles larger than the staging window (8192 keys: two windows), every
+    bucket-count instance and payload width, several work items and a ragged
+    last tile"""
+    n = 3 * 32768 + 12_345
+    x, pay = synth.make("lognormal" if k != 512 else "dup_heavy", n, payload_bytes=pw)
+    cfg = dict(k=k, cutoff=256, max_zlevels=8, chunk=32768, tile=tile)
+    say(f"case tile {cfg} pw={pw}")
+    kk, p, st = gpu_sort(x, pay, cfg)
+    assert st["device_error"] == 0, st
+    ok, op, _ = oracle.sort(x, pay, k=k, cutoff=256, max_zlevels=8)
+    assert np.array_equal(kk, ok)
+    if pw:
+        assert np.array_equal(p, op)
+
+
+@pytest.mark.parametrize("name,pw", [("lognormal", 8), ("uniform_1e8", 4)])
+def test_full_size_bench_configuration(name, pw):
+    """10^8 keys in the configuration the benchmark times (the library's
+    autotuner picks it): sorted, the index payload a permutation carrying its
+    key, equal keys in input order -- together these fix the output"""
+    n = 10**8
+    x, idx = synth.make(name, n, payload_bytes=pw)
+    tk, tp = to_dev(x, idx)
+    cfg = zs.zsort_autotune(tk, tp)
+    say(f"case full size {name} {cfg}")
+    zs.zsort_stable_ex(tk, tp, cfg)
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] == 0
+    k, p = from_dev(tk, tp, idx.dtype)
+    del tk, tp
+    check_stable_sorted(x, k, p)
