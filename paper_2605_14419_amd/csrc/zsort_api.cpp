@@ -76,9 +76,9 @@ struct Layout {
   size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
       off_hard[2],
       off_status, off_part,
-      off_bstart, off_trace, off_thist, total;
+      off_bstart, off_subpre, off_tiles[2], off_trace, off_thist, total;
   size_t status_bytes;
-  uint32_t seg_cap, work_cap, leaf_cap, status_cap;
+  uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -120,6 +120,12 @@ Layout plan(const Shape& s) {
   L.off_status = take(L.status_bytes);
   L.off_part = take(work_cap * 10 * 8);
   L.off_bstart = take(std::max<size_t>(seg_cap * (size_t)s.k, (size_t)s.kfirst) * 4);
+  // 8192-key tiles: one row of k 16-bit prefix counts per 8192 keys
+  const size_t krow = std::max<size_t>((size_t)s.k, s.kfirst <= 1024 ? (size_t)s.kfirst : 0);
+  L.off_subpre = take(s.tile == 8192 ? ((n >> 13) + 2) * krow * 2 : 0);
+  // and the tile lists: at most one partial tile per segment
+  L.tile_cap = s.tile == 8192 ? (uint32_t)((n >> 13) + seg_cap + 2) : 0u;
+  for (int i = 0; i < 2; ++i) L.off_tiles[i] = take((size_t)L.tile_cap * 8);
   L.off_trace = take((size_t)s.trace_cap * sizeof(zs::TraceRec));
   L.off_thist = take((size_t)s.trace_hist_cap * 4);
   L.total = align_up(o, 256);
@@ -224,6 +230,7 @@ int check_cfg(const zsort_config* c) {
   if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
   if (c->tile != 2048 && c->tile != 4096 && c->tile != 8192) return ZSORT_EINVAL;
   if (c->tile > 2048 && (c->k > 1024 || c->chunk % c->tile)) return ZSORT_EINVAL;
+  if (c->tile == 8192 && c->chunk > 32768) return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 
@@ -306,6 +313,8 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
   ws.status = (uint64_t*)(w->base + L.off_status);
   ws.part = (uint64_t*)(w->base + L.off_part);
   ws.bstart = (uint32_t*)(w->base + L.off_bstart);
+  ws.subpre = (uint16_t*)(w->base + L.off_subpre);
+  for (int i = 0; i < 2; ++i) ws.tiles[i] = (uint64_t*)(w->base + L.off_tiles[i]);
   ws.ctl = (zs::Ctl*)(w->base + L.off_ctl);
   ws.trace = w->shape.trace_cap ? (zs::TraceRec*)(w->base + L.off_trace) : nullptr;
   ws.trace_hist = w->shape.trace_hist_cap ? (uint32_t*)(w->base + L.off_thist) : nullptr;
@@ -313,6 +322,7 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
   ws.trace_hist_cap = (uint32_t)w->shape.trace_hist_cap;
   ws.seg_cap = L.seg_cap;
   ws.work_cap = L.work_cap;
+  ws.tile_cap = L.tile_cap;
   ws.leaf_cap = L.leaf_cap;
   ws.status_cap = L.status_cap;
   ws.p.k = c.k;

@@ -80,6 +80,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nleafw[2];            // wave jobs: groups of <= kWaveCap keys
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
+  uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list
   uint32_t tick[kMaxLevels];     // in-order chunk tickets of the hist pass
   uint32_t epoch;                // changes every call; tags look-back words
   uint32_t error;                // nonzero: a capacity or wait limit was hit
@@ -166,7 +167,7 @@ struct Params {
   int32_t cutoff;        // leaf size
   int32_t max_zlevels;
   int32_t chunk;         // keys per work item
-  int32_t tile;          // keys per scatter tile (2048 or 4096)
+  int32_t tile;          // keys per scatter tile (2048, 4096 or 8192)
   int32_t pw;            // payload bytes: 0, 4, 8
 };
 
@@ -182,11 +183,14 @@ struct Ws {
   uint64_t* status;      // look-back words, [slot][k]
   uint64_t* part;        // per work item: 8 digit sums, min, max (moments pass)
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
+  uint16_t* subpre;      // 8192-key tiles: each cluster's count in a work item before
+                         // the tile that starts at key position p, row p >> 13, [row][k]
+  uint64_t* tiles[2];    // 8192-key tiles: (segment << 32) | (chunk << 2) | tile, the scatter's items
   Ctl* ctl;
   TraceRec* trace;       // may be null
   uint32_t* trace_hist;
   uint32_t trace_cap, trace_hist_cap;
-  uint32_t seg_cap, work_cap, leaf_cap, status_cap;
+  uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
   Params p;
   LMap lm;
 };

@@ -357,7 +357,7 @@ __global__ void k_reset(Ws ws) {
     c->epoch = c->epoch + 1u;
     for (int s = 0; s < 2; ++s) {
       c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nhard[s] = 0;
-      c->nstatus[s] = 0;
+      c->nstatus[s] = 0; c->ntile[s] = 0;
     }
     c->error = 0;
     c->ntrace = 0;
@@ -388,6 +388,16 @@ __device__ bool push_leaf(Ws& ws, int S, uint64_t start, uint32_t count, uint32_
   return true;
 }
 
+// 8192-key tiles: scatter items per work item (1 with smaller tiles)
+__device__ __forceinline__ uint32_t tiles_per_item(const Ws& ws) {
+  return ws.p.tile == 8192 ? (uint32_t)((uint32_t)ws.p.chunk >> 13) : 1u;
+}
+
+// tile u of segment si: (segment << 32) | (chunk << 2) | tile in the chunk
+__device__ __forceinline__ uint64_t tile_entry(uint32_t si, uint32_t u, uint32_t nsub) {
+  return ((uint64_t)si << 32) | ((u / nsub) << 2) | (u % nsub);
+}
+
 __device__ void make_root_seg(Ws& ws, uint32_t slot_seg, uint64_t start, uint64_t count,
                               uint32_t first_work, uint32_t nch, uint32_t status_base) {
   Seg& s = ws.segs[0][slot_seg];
@@ -402,6 +412,16 @@ __device__ void make_root_seg(Ws& ws, uint32_t slot_seg, uint64_t start, uint64_
   s.status_base = status_base;
   s.parent = -1;
   seg_clear_acc(s);
+}
+
+// tile list of the single root segment [0, n) (8192-key tiles only)
+__device__ void init_root_tiles(Ws& ws, uint64_t n) {
+  const uint32_t nsub = tiles_per_item(ws);
+  if (nsub == 1) return;
+  const uint32_t ntl = (uint32_t)((n + 8191) >> 13);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ws.ctl->ntile[0] = ntl;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < ntl; u += gridDim.x * blockDim.x)
+    ws.tiles[0][u] = tile_entry(0u, u, nsub);
 }
 
 // one array [0, n): root segment (n > cutoff) or a single leaf
@@ -424,6 +444,7 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
     ws.work[0][i] = (uint64_t)i;  // segment 0, chunk i
+  init_root_tiles(ws, n);
 }
 
 // empties the lists of one slot (a level that runs no moments pass)
@@ -431,7 +452,7 @@ __global__ void k_reset_lists(Ws ws, int slot) {
   Ctl* c = ws.ctl;
   if (threadIdx.x == 0) {
     c->nseg[slot] = 0; c->nwork[slot] = 0; c->nleaf[slot] = 0; c->nleafw[slot] = 0;
-    c->nhard[slot] = 0; c->nstatus[slot] = 0;
+    c->nhard[slot] = 0; c->nstatus[slot] = 0; c->ntile[slot] = 0;
   }
 }
 
@@ -458,6 +479,7 @@ __global__ void k_init_learned(Ws ws, uint64_t n) {
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
     ws.work[0][i] = (uint64_t)i;
+  init_root_tiles(ws, n);
 }
 
 // independent arrays [off[i], off[i+1]); offsets were validated by k_check_offsets
@@ -493,6 +515,16 @@ __global__ void k_init_segments(Ws ws, const int64_t* off, int32_t nseg) {
     }
     make_root_seg(ws, si, a, len, wi, nch, sb);
     for (uint32_t j = 0; j < nch; ++j) ws.work[0][wi + j] = ((uint64_t)si << 32) | j;
+    const uint32_t nsub = tiles_per_item(ws);
+    if (nsub > 1) {
+      const uint32_t ntl = (uint32_t)((len + 8191) >> 13);
+      const uint32_t ti = atomicAdd(&c->ntile[0], ntl);
+      if (ti + ntl > ws.tile_cap) {
+        atomicOr(&c->error, ERR_WORKCAP);
+        continue;
+      }
+      for (uint32_t u = 0; u < ntl; ++u) ws.tiles[0][ti + u] = tile_entry(si, u, nsub);
+    }
   }
 }
 
@@ -606,7 +638,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   if (call_failed(c)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
     c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nhard[N] = 0;
-    c->nstatus[N] = 0;
+    c->nstatus[N] = 0; c->ntile[N] = 0;
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
   const uint64_t* __restrict__ x = ws.keys[S];
@@ -704,14 +736,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Ws ws, int L) {
 // ---------------------------------------------------------------------------
 template <int KMAX>
 struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned thresholds)
-  uint32_t h[KMAX];       // histogram, later totals
+  uint32_t h[KMAX];       // histogram, later totals (8192-key tiles: 16-bit counts of
+                          // tiles 0 and 1 of the work item until the totals are formed)
+  uint32_t hq[KMAX <= 1024 ? KMAX : 1];   // 16-bit counts of tiles 2 and 3
   uint32_t bst[KMAX];     // exclusive starts
   uint32_t t0[KMAX];      // scratch arrays for classification
   uint32_t t1[KMAX];
   uint32_t t2[KMAX];
   uint32_t sh[kWaves + 2];
   uint32_t w;
-  uint32_t base_seg, base_work, base_status, base_leaf;
+  uint32_t base_seg, base_work, base_status, base_leaf, base_tile;
 };
 
 template <int KMAX>
@@ -738,25 +772,33 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     sm.t0[b] = child ? 1u : 0u;
     sm.t1[b] = nch;
     sm.t2[b] = nch > 1 ? nch : 0u;
+    if constexpr (KMAX <= 1024) sm.hq[b] = child ? (n + 8191u) >> 13 : 0u;  // 8192-key tiles
   }
   __syncthreads();
   const uint32_t nchild = block_scan_lds(sm.t0, k, sm.sh);
   const uint32_t nwork = block_scan_lds(sm.t1, k, sm.sh);
   const uint32_t nstat = block_scan_lds(sm.t2, k, sm.sh);
+  const uint32_t nsub = tiles_per_item(ws);
+  uint32_t ntiles = 0;
+  if constexpr (KMAX <= 1024)
+    if (nsub > 1) ntiles = block_scan_lds(sm.hq, k, sm.sh);
   if (t == 0) {
     sm.base_seg = nchild ? atomicAdd(&c->nseg[N], nchild) : 0u;
     sm.base_work = nwork ? atomicAdd(&c->nwork[N], nwork) : 0u;
     sm.base_status = nstat ? atomicAdd(&c->nstatus[N], nstat) : 0u;
+    sm.base_tile = ntiles ? atomicAdd(&c->ntile[N], ntiles) : 0u;
     if (nchild) {
       atomicMax(&c->max_level, (uint32_t)(L + 1));
       if (sm.base_seg + nchild > ws.seg_cap) atomicOr(&c->error, ERR_SEGCAP);
       if (sm.base_work + nwork > ws.work_cap) atomicOr(&c->error, ERR_WORKCAP);
       if (sm.base_status + nstat > ws.status_cap) atomicOr(&c->error, ERR_STATUSCAP);
+      if (sm.base_tile + ntiles > ws.tile_cap && ntiles) atomicOr(&c->error, ERR_WORKCAP);
     }
   }
   __syncthreads();
   const bool fits = sm.base_seg + nchild <= ws.seg_cap && sm.base_work + nwork <= ws.work_cap &&
-                    sm.base_status + nstat <= ws.status_cap;
+                    sm.base_status + nstat <= ws.status_cap &&
+                    (ntiles == 0 || sm.base_tile + ntiles <= ws.tile_cap);
   const double scale = (double)k / 4.0;
   const bool parent_r = sg.kind == KIND_RMAP;
   const bool parent_l = sg.kind == KIND_LMAP;  // children take their exact mean
@@ -813,6 +855,18 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       }
       const uint32_t b = sm.t2[lo];
       ws.work[N][sm.base_work + j] = ((uint64_t)(sm.base_seg + lo) << 32) | (j - sm.t1[b]);
+    }
+    // 8192-key tiles: the scatter's items, child by child in work-item order
+    if constexpr (KMAX <= 1024) {
+      for (uint32_t j = t; j < ntiles; j += kBlock) {
+        uint32_t lo = 0, hi = nchild;  // invariant: hq[bucket(lo)] <= j
+        while (hi - lo > 1) {
+          uint32_t mid = (lo + hi) >> 1;
+          if (sm.hq[sm.t2[mid]] <= j) lo = mid; else hi = mid;
+        }
+        const uint32_t b = sm.t2[lo];
+        ws.tiles[N][sm.base_tile + j] = tile_entry(sm.base_seg + lo, j - sm.hq[b], nsub);
+      }
     }
   }
   __syncthreads();
@@ -925,6 +979,21 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   __syncthreads();
 }
 
+// one key of cluster b at offset `off` in its work item.  With 8192-key
+// scatter tiles (nsub > 1) the count goes to the key's tile: two tiles share
+// a word, 16 bits each (a tile holds at most 8192 keys, so the halves never
+// carry into each other).
+template <int KMAX>
+__device__ __forceinline__ void hist_add(HistSmem<KMAX>& sm, uint32_t b, uint64_t off,
+                                         uint32_t nsub) {
+  if (KMAX > 1024 || nsub == 1) {
+    atomicAdd(&sm.h[b], 1u);
+  } else {
+    const uint32_t tile = (uint32_t)(off >> 13);
+    atomicAdd((tile & 2u) ? &sm.hq[b] : &sm.h[b], (tile & 1u) ? 0x10000u : 1u);
+  }
+}
+
 // LM: 0 plain; the learned passes (every segment has KIND_LMAP): 1 with
 // thresholds, 2 with the MLP evaluated per key.  Separate instances, so that
 // the per-key MLP does not raise the register count of the other two.
@@ -940,6 +1009,9 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   const uint64_t* __restrict__ x = ws.keys[S];
   const uint32_t tag = level_tag(c->epoch, L);
   const int t = threadIdx.x;
+  // tiles of the scatter per work item, each with its own starts (8192-key
+  // tiles only, at most 4)
+  const uint32_t nsub = tiles_per_item(ws);
 
   while (true) {
     if (t == 0) sm.w = atomicAdd(&c->tick[L], 1u);
@@ -954,7 +1026,10 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     const MapP mp = map_of(sg, k);
     const uint64_t beg = sg.start + (uint64_t)ci * ch;
     const uint64_t end = min(beg + ch, sg.start + sg.count);
-    for (int b = t; b < k; b += kBlock) sm.h[b] = 0;
+    for (int b = t; b < k; b += kBlock) {
+      sm.h[b] = 0;
+      if constexpr (KMAX <= 1024) sm.hq[b] = 0;
+    }
     __syncthreads();
     if constexpr (LM != 0) {
       // learned map: cluster = number of the segment's window thresholds
@@ -974,14 +1049,34 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
         uint32_t b;
         if constexpr (LM == 2) b = mlp_cluster(*ws.lm.par, v, smin, smax, k);
         else b = thr_cluster(thr, nt, top, v);
-        atomicAdd(&sm.h[b], 1u);
+        hist_add(sm, b, i - beg, nsub);
         ids[i] = (uint16_t)b;
       });
     } else {
-      for_each_key<4>(x, beg, end,
-                      [&](uint64_t, uint64_t v) { atomicAdd(&sm.h[bucket_of(v, mp)], 1u); });
+      for_each_key<4>(x, beg, end, [&](uint64_t i, uint64_t v) {
+        hist_add(sm, bucket_of(v, mp), i - beg, nsub);
+      });
     }
     __syncthreads();
+    if (KMAX <= 1024 && nsub > 1) {
+      // per-tile counts -> the totals, and for every later tile of the item
+      // each cluster's count before it (the scatter's start inside the item)
+      for (int b = t; b < k; b += kBlock) {
+        const uint32_t v0 = sm.h[b], v1 = sm.hq[b];
+        const uint32_t cnt[4] = {v0 & 0xFFFFu, v0 >> 16, v1 & 0xFFFFu, v1 >> 16};
+        uint32_t run = cnt[0];
+#pragma unroll
+        for (uint32_t q = 1; q < 4; ++q) {
+          if (q < nsub) {
+            const uint64_t p = beg + ((uint64_t)q << 13);
+            if (p < end) ws.subpre[(p >> 13) * (uint64_t)k + b] = (uint16_t)run;
+            run += cnt[q];
+          }
+        }
+        sm.h[b] = run;
+      }
+      __syncthreads();
+    }
     const uint32_t nch = sg.nchunks;
     if (nch > 1) {
       uint64_t* st0 = ws.status + (uint64_t)sg.status_base * (uint64_t)k;
@@ -1077,22 +1172,48 @@ __global__ void __launch_bounds__(SB, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, in
   const uint32_t g = blockIdx.x;
   const uint32_t slot = (per_xcd * 8u == G) ? ((g % 8u) * per_xcd + g / 8u) : g;
 
-  for (uint32_t w0 = 0; w0 < nw; w0 += G) {
-    const uint32_t w = w0 + slot;
-    if (w >= nw) continue;
-    const uint64_t item = ws.work[S][w];
-    const uint32_t si = (uint32_t)(item >> 32), ci = (uint32_t)item;
+  // With 8192-key tiles every tile of a work item is an item of its own (the
+  // histogram pass left each cluster's count before it), so neighbouring
+  // workgroups write neighbouring runs of each cluster at the same time;
+  // otherwise a workgroup takes a work item's tiles in order.
+  // (a level whose segments were made by a pass with other tiles has no
+  // tile list: then the work items are taken whole)
+  const uint32_t ntl = min(c->ntile[S], ws.tile_cap);
+  const uint32_t nsub = ntl > 0 ? tiles_per_item(ws) : 1u;
+  const uint64_t span = ch / nsub;
+  const uint32_t nwt = nsub > 1 ? ntl : nw;
+  const uint32_t ns = min(c->nseg[S], ws.seg_cap);
+
+  for (uint32_t w0 = 0; w0 < nwt; w0 += G) {
+    const uint32_t wt = w0 + slot;
+    if (wt >= nwt) continue;
+    uint32_t si, ci, sub = 0;
+    if (nsub > 1) {
+      const uint64_t e = ws.tiles[S][wt];
+      si = (uint32_t)(e >> 32);
+      ci = (uint32_t)e >> 2;
+      sub = (uint32_t)e & 3u;
+    } else {
+      const uint64_t item = ws.work[S][wt];
+      si = (uint32_t)(item >> 32);
+      ci = (uint32_t)item;
+    }
+    if (si >= ns) continue;
     const Seg& sg = ws.segs[S][si];
     if (sg.kind == KIND_IDENT) continue;
     const MapP mp = map_of(sg, k);
     const bool lmap = sg.kind == KIND_LMAP;
-    const uint64_t beg = sg.start + (uint64_t)ci * ch;
-    const uint64_t end = min(beg + ch, sg.start + sg.count);
+    const uint64_t cbeg = sg.start + (uint64_t)ci * ch;
+    const uint64_t beg = cbeg + (uint64_t)sub * span;
+    const uint64_t end = min(beg + span, sg.start + sg.count);
+    if (beg >= end) continue;
     const uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
     const uint64_t* stp = (ci > 0) ? ws.status + (uint64_t)(sg.status_base + ci - 1) * (uint64_t)k : nullptr;
+    const uint16_t* spp = sub > 0 ? ws.subpre + (beg >> 13) * (uint64_t)k : nullptr;
     for (int b = t; b < k; b += SB) {
       uint64_t base = sg.start + gb[b];
       if (stp) base += stp[b] & kValMask;
+      if (spp) base += spp[b];
       sm.gbase[b] = (uint32_t)base;
     }
     // segment bounds in registers (a reference into global memory would be

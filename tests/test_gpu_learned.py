@@ -213,6 +213,20 @@ def test_learned_sort_matches_oracle(wl, n, pw):
     assert np.array_equal(ok, ek) and np.array_equal(op, ep)
 
 
+@pytest.mark.parametrize("wl,n,pw,buckets", [("gmm", 1 << 22, 4, 4096), ("lognormal", 1 << 21, 8, 4096),
+                                             ("gmm", 3_000_017, 4, 512)])
+def test_learned_sort_with_8192_key_tiles(wl, n, pw, buckets):
+    """learned first pass (one or two stages) followed by z-score levels whose
+    scatter takes 8192-key tiles as items of their own"""
+    keys, pay = synth.make(wl, n, payload_bytes=pw)
+    cfg = dict(k=512, cutoff=2048, max_zlevels=8, chunk=32768, tile=8192)
+    say(f"case learned sort tile 8192 {wl} n={n} pw={pw} buckets={buckets}")
+    ok, op, rep, st = learned_sort(keys, pay, cfg, dict(buckets=buckets))
+    assert rep["used_learned"] == 1 and rep["fallback"] == 0, rep
+    ek, ep, _ = oracle.sort(keys, pay, k=1024, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(ok, ek) and np.array_equal(op, ep)
+
+
 def test_first_pass_histogram_matches_oracle_with_given_params(mix):
     keys, idx, s = mix
     smin, smax = int(s[0]), int(s[-1])

@@ -244,3 +244,19 @@ def test_full_size_bench_configuration(name, pw):
     k, p = from_dev(tk, tp, idx.dtype)
     del tk, tp
     check_stable_sorted(x, k, p)
+
+
+@pytest.mark.parametrize("chunk", [8192, 16384])
+def test_segmented_tile8192_vs_oracle(chunk):
+    """8192-key tiles as work items of their own (one, two per chunk) across
+    many segments, each segment's starts taken from the histogram pass"""
+    keys, off, idx = synth.segments(300, 91, median=20_000, hi=120_000)
+    cfg = dict(k=512, cutoff=512, max_zlevels=8, chunk=chunk, tile=8192)
+    say(f"case segmented tile 8192 n={keys.size} {cfg}")
+    tk, tp = to_dev(keys, idx)
+    zs.zsort_stable_segmented(tk, torch.from_numpy(off).to(DEV), tp, cfg)
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] == 0
+    k, p = from_dev(tk, tp)
+    ok, oi = oracle.sort_segmented(keys, off, idx, k=512, cutoff=512, max_zlevels=8)
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
