@@ -1671,7 +1671,8 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
 
 // ---------------------------------------------------------------------------
 // fast local sort: one counting pass on the top bits of x - min (about one
-// bucket per key), then a tiny insertion sort inside each bucket.  Works on
+// bucket per key), then each key's place inside its bucket from the number
+// of smaller words there.  Works on
 // the unique words ((x - min) << 12) | position, so the result is the stable
 // sort.  Returns false, before writing anything, if the group's range needs
 // more than 51 bits or some bucket holds more than kBucketMax keys; such
@@ -1840,25 +1841,24 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
     }
   }
   team_sync<TW>();
-  // insertion sort inside each bucket: bucket b spans [end(b-1), end(b))
-  for (uint32_t b = tid; b < nb; b += TT) {
-    const uint32_t e = c16_get(cnt, b);
-    const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
-    for (uint32_t i = s0 + 1; i < e; ++i) {
+  // Bucket b now spans [end(b-1), end(b)).  A word's place in the output is
+  // its bucket's start plus the number of smaller words in the bucket (the
+  // words are unique).  Keys and payloads go straight to their places (a
+  // permutation inside each bucket: nearly sequential).
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * TT + tid;
+    if (i < n) {
       const uint64_t v = kb[i];
-      uint32_t j = i;
-      while (j > s0 && kb[j - 1] > v) {
-        kb[j] = kb[j - 1];
-        --j;
-      }
-      kb[j] = v;
+      const uint32_t b = (uint32_t)((v >> 12) >> shb);
+      const uint32_t e = c16_get(cnt, b);
+      const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
+      uint32_t rank = 0;
+      for (uint32_t j = s0; j < e; ++j) rank += kb[j] < v ? 1u : 0u;
+      const uint32_t p = min(s0 + rank, n - 1);
+      dst[start + p] = (v >> 12) + mn;
+      if constexpr (PW != 0) pay_store<PW>(pdst, start + p, pb[v & 4095u]);
     }
-  }
-  team_sync<TW>();
-  for (uint32_t i = tid; i < n; i += TT) {
-    const uint64_t v = kb[i];
-    dst[start + i] = (v >> 12) + mn;
-    if constexpr (PW != 0) pay_store<PW>(pdst, start + i, pb[v & 4095u]);
   }
   team_sync<TW>();
   return true;
