@@ -74,6 +74,7 @@ struct Shape {
 
 struct Layout {
   size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
+      off_leavesm[2],
       off_hard[2],
       off_status, off_part,
       off_bstart, off_subpre, off_tiles[2], off_trace, off_thist, total;
@@ -112,6 +113,7 @@ Layout plan(const Shape& s) {
     L.off_work[i] = take(work_cap * 8);
     L.off_leaves[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_leavesw[i] = take(leaf_cap * sizeof(zs::Leaf));
+    L.off_leavesm[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_hard[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
   // look-back words: [slot][k]; a learned first pass has one root of
@@ -308,6 +310,7 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
     ws.work[i] = (uint64_t*)(w->base + L.off_work[i]);
     ws.leaves[i] = (zs::Leaf*)(w->base + L.off_leaves[i]);
     ws.leavesw[i] = (zs::Leaf*)(w->base + L.off_leavesw[i]);
+    ws.leavesm[i] = (zs::Leaf*)(w->base + L.off_leavesm[i]);
     ws.hard[i] = (zs::Leaf*)(w->base + L.off_hard[i]);
   }
   ws.status = (uint64_t*)(w->base + L.off_status);

@@ -27,6 +27,7 @@ constexpr int kKMax = 4096;            // largest clusters-per-pass supported
 constexpr int kLocalCap = 4096;        // largest group the fallback local sort takes
 constexpr int kBlockCap = 2048;        // largest group (= largest cutoff) of the fast local sort
 constexpr int kWaveCap = 512;          // largest group one wave sorts
+constexpr int kMidCap = 1024;          // largest block job that one wave of k_local_mid sorts
 constexpr int kWindow = 256;           // leaf-group window; larger leaves sort alone
 constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
 
@@ -78,6 +79,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nwork[2];
   uint32_t nleaf[2];             // block jobs: big leaves and copies
   uint32_t nleafw[2];            // wave jobs: groups of <= kWaveCap keys
+  uint32_t nleafm[2];            // one-wave jobs of kWaveCap < n <= kMidCap keys
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
   uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list
@@ -179,6 +181,7 @@ struct Ws {
   uint64_t* work[2];     // (segment << 32) | chunk
   Leaf* leaves[2];       // block jobs
   Leaf* leavesw[2];      // wave jobs
+  Leaf* leavesm[2];      // mid-size jobs (one wave, up to kMidCap keys)
   Leaf* hard[2];         // jobs for the fallback local sort
   uint64_t* status;      // look-back words, [slot][k]
   uint64_t* part;        // per work item: 8 digit sums, min, max (moments pass)

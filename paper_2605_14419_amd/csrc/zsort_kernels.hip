@@ -356,7 +356,7 @@ __global__ void k_reset(Ws ws) {
   if (t == 0) {
     c->epoch = c->epoch + 1u;
     for (int s = 0; s < 2; ++s) {
-      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nhard[s] = 0;
+      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nleafm[s] = 0; c->nhard[s] = 0;
       c->nstatus[s] = 0; c->ntile[s] = 0;
     }
     c->error = 0;
@@ -374,13 +374,14 @@ __device__ bool push_leaf(Ws& ws, int S, uint64_t start, uint32_t count, uint32_
                           uint32_t src) {
   Ctl* c = ws.ctl;
   const bool small = !(flags & LF_COPY) && count <= (uint32_t)kWaveCap;
-  uint32_t* ctr = small ? &c->nleafw[S] : &c->nleaf[S];
+  const bool mid = !(flags & LF_COPY) && !small && count <= (uint32_t)kMidCap;
+  uint32_t* ctr = small ? &c->nleafw[S] : (mid ? &c->nleafm[S] : &c->nleaf[S]);
   const uint32_t li = atomicAdd(ctr, 1u);
   if (li >= ws.leaf_cap) {
     atomicOr(&c->error, ERR_LEAFCAP);
     return false;
   }
-  Leaf& lf = small ? ws.leavesw[S][li] : ws.leaves[S][li];
+  Leaf& lf = small ? ws.leavesw[S][li] : (mid ? ws.leavesm[S][li] : ws.leaves[S][li]);
   lf.start = (uint32_t)start;
   lf.count = count;
   lf.flags = flags;
@@ -451,7 +452,7 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
 __global__ void k_reset_lists(Ws ws, int slot) {
   Ctl* c = ws.ctl;
   if (threadIdx.x == 0) {
-    c->nseg[slot] = 0; c->nwork[slot] = 0; c->nleaf[slot] = 0; c->nleafw[slot] = 0;
+    c->nseg[slot] = 0; c->nwork[slot] = 0; c->nleaf[slot] = 0; c->nleafw[slot] = 0; c->nleafm[slot] = 0;
     c->nhard[slot] = 0; c->nstatus[slot] = 0; c->ntile[slot] = 0;
   }
 }
@@ -637,7 +638,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   const int S = L & 1, N = S ^ 1;
   if (call_failed(c)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
-    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nhard[N] = 0;
+    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nleafm[N] = 0; c->nhard[N] = 0;
     c->nstatus[N] = 0; c->ntile[N] = 0;
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
@@ -745,7 +746,7 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t t2[KMAX];
   uint32_t sh[kWaves + 2];
   uint32_t w;
-  uint32_t base_seg, base_work, base_status, base_leaf, base_tile;
+  uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid;
 };
 
 template <int KMAX>
@@ -901,32 +902,39 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   for (int b = t; b < k; b += kBlock)
     if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
   __syncthreads();
-  uint32_t my_small = 0, my_big = 0;
+  uint32_t my_small = 0, my_mid = 0, my_big = 0;
   for (uint32_t i = t; i < nb; i += kBlock) {
     if (!(bpos[i] >> 31)) continue;
     const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
     const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
-    if (p1 - p0 <= (uint32_t)kWaveCap) ++my_small; else ++my_big;
+    if (p1 - p0 <= (uint32_t)kWaveCap) ++my_small;
+    else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
+    else ++my_big;
   }
-  uint32_t nsmall, nbig;
+  uint32_t nsmall, nmid, nbig;
   const uint32_t off_small = block_excl_sum(my_small, sm.sh, &nsmall);
+  const uint32_t off_mid = block_excl_sum(my_mid, sm.sh, &nmid);
   const uint32_t off_big = block_excl_sum(my_big, sm.sh, &nbig);
   if (t == 0) {
     sm.base_leaf = nsmall ? atomicAdd(&c->nleafw[S], nsmall) : 0u;
+    sm.base_mid = nmid ? atomicAdd(&c->nleafm[S], nmid) : 0u;
     sm.base_status = nbig ? atomicAdd(&c->nleaf[S], nbig) : 0u;  // (reused as the big-list base)
-    if (nsmall + nbig) atomicAdd(&c->n_leafgroups, nsmall + nbig);
-    if (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_status + nbig > ws.leaf_cap)
+    if (nsmall + nmid + nbig) atomicAdd(&c->n_leafgroups, nsmall + nmid + nbig);
+    if (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
+        sm.base_status + nbig > ws.leaf_cap)
       atomicOr(&c->error, ERR_LEAFCAP);
   }
   __syncthreads();
-  if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_status + nbig <= ws.leaf_cap) {
-    uint32_t os = sm.base_leaf + off_small, ob = sm.base_status + off_big;
+  if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
+      sm.base_status + nbig <= ws.leaf_cap) {
+    uint32_t os = sm.base_leaf + off_small, om = sm.base_mid + off_mid, ob = sm.base_status + off_big;
     for (uint32_t i = t; i < nb; i += kBlock) {
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
       const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
       const bool small = p1 - p0 <= (uint32_t)kWaveCap;
-      Leaf& lf = small ? ws.leavesw[S][os++] : ws.leaves[S][ob++];
+      const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
+      Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
       lf.start = (uint32_t)(sg.start + p0);
       lf.count = p1 - p0;
       lf.flags = 0;
@@ -1931,23 +1939,25 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   using P = typename PayT<PW>::T;
   const uint32_t gs = gridDim.x * kWaves;
   uint32_t g = blockIdx.x * kWaves + wv;
-  Leaf lf{};
+  // (and the descriptor of the group after it, so that the next group's
+  // loads need not wait for their descriptor)
+  Leaf lf{}, nf{};
   uint64_t key[RW];
   P pay[RW];
   if (g < nlw) {
     lf = ws.leavesw[S][g];
     group_load<PW, kWave, RW>(ws.keys[lf.src], ws.pay[lf.src], lf.start, lf.count, ln, key, pay);
   }
+  if (g + gs < nlw) nf = ws.leavesw[S][g + gs];
   for (; g < nlw; g += gs) {
     const uint32_t gn = g + gs;
-    Leaf nf{};
+    Leaf nnf{};
+    if (gn + gs < nlw) nnf = ws.leavesw[S][gn + gs];
     uint64_t nkey[RW];
     P npay[RW];
-    if (gn < nlw) {
-      nf = ws.leavesw[S][gn];
+    if (gn < nlw)
       group_load<PW, kWave, RW>(ws.keys[nf.src], ws.pay[nf.src], nf.start, nf.count, ln, nkey,
                                 npay);
-    }
     const uint64_t* __restrict__ src = ws.keys[lf.src];
     const void* psrc = ws.pay[lf.src];
     const uint32_t n = lf.count;
@@ -1963,6 +1973,7 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
       if (!ok && ln == 0) push_hard(ws, S, lf);
     }
     lf = nf;
+    nf = nnf;
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       key[r] = nkey[r];
@@ -1982,6 +1993,40 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   }
 }
 
+// Groups of kWaveCap < n <= kMidCap keys: one wave each (a workgroup of one
+// wave, 16 keys per lane), which costs far less per key than a whole
+// workgroup on a group of barely more than kWaveCap keys.
+template <int PW>
+struct MidSmem {
+  uint64_t k[kMidCap];
+  typename PayT<PW>::T pay[PW ? kMidCap : 1];
+  uint32_t cnt[kMidCap / 2];
+};
+
+template <int PW>
+__global__ void __launch_bounds__(kWave) k_local_mid(Ws ws, int L) {
+  __shared__ MidSmem<PW> sm;
+  Ctl* c = ws.ctl;
+  if (call_failed(c)) return;
+  const int S = L & 1;
+  const uint32_t nl = min(c->nleafm[S], ws.leaf_cap);
+  uint64_t* __restrict__ dst = ws.keys[0];
+  void* pdst = ws.pay[0];
+  const uint32_t ln = lane();
+  uint64_t moved = 0;
+  for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
+    const Leaf lf = ws.leavesm[S][g];
+    const uint32_t n = lf.count;
+    if (n > (uint32_t)kMidCap) continue;   // (never: the list holds kWaveCap < n <= kMidCap)
+    moved += n;
+    const bool ok = fast_sort<PW, 1, kMidCap / kWave>(sm.k, sm.pay, sm.cnt, nullptr, nullptr,
+                                                      nullptr, ws.keys[lf.src], ws.pay[lf.src],
+                                                      dst, pdst, lf.start, n, ln);
+    if (!ok && ln == 0) push_hard(ws, S, lf);
+  }
+  if (ln == 0 && moved) atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)moved);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1995,6 +2040,24 @@ static const void* stage_fn(int stage) {
     case STAGE_LOCAL: return (const void*)k_local<PW>;
     default: return (const void*)k_local_hard<PW>;
   }
+}
+
+// resident one-wave workgroups of k_local_mid on the whole device
+template <int PW>
+static int mid_grid() {
+  static int g = 0;
+  if (g == 0) {
+    int nb = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_local_mid<PW>, kWave, 0) !=
+            hipSuccess || nb < 1)
+      nb = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 1;
+    g = (nb < 16 ? nb : 16) * cus;
+  }
+  return g;
 }
 
 template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
@@ -2020,6 +2083,7 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       break;
     case STAGE_LOCAL:
       hipLaunchKernelGGL((k_local<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      hipLaunchKernelGGL((k_local_mid<PW>), dim3(mid_grid<PW>()), dim3(kWave), 0, st, ws, L);
       break;
     default:
       hipLaunchKernelGGL((k_local_hard<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
