@@ -279,8 +279,12 @@ def roofline(kt, stats, pw, steps, traffic_file, cfg):
             "launches": launches}
 
 
+# kernel -> stage; the local stage launches two kernels (groups of up to 512
+# keys, then one wave per group of 513..1024): the first counts the launches
 STAGE_OF_KERNEL = (("k_moments", "moments"), ("k_finalize", "finalize"), ("k_hist", "hist"),
-                   ("k_scatter", "scatter"), ("k_local_hard", "local_hard"), ("k_local", "local"))
+                   ("k_scatter", "scatter"), ("k_local_hard", "local_hard"),
+                   ("k_local_mid", "local"), ("k_local", "local"))
+SECOND_KERNELS = ("k_local_mid",)
 
 
 def _stage_of(name):
@@ -288,6 +292,10 @@ def _stage_of(name):
         if pat + "<" in name or pat + "(" in name:
             return st
     return None
+
+
+def _is_second(name):
+    return any(p + "<" in name or p + "(" in name for p in SECOND_KERNELS)
 
 
 def _csv(dirname, suffix):
@@ -327,8 +335,10 @@ def summarize_profiles(d, workload, cfg):
         if st != "-":
             a = per_stage.setdefault(st, [0, 0])
             a[0] += int(r["TotalDurationNs"])
-            a[1] += int(r["Calls"])
-    lines += ["", "Per stage (all template instances):", "", "| stage | calls | total ms | avg us |",
+            if not _is_second(r["Name"]):
+                a[1] += int(r["Calls"])
+    lines += ["", "Per stage (all template instances; the local stage's calls count its first "
+              "kernel):", "", "| stage | calls | total ms | avg us |",
               "|---|---|---|---|"]
     for st, (ns, c) in sorted(per_stage.items(), key=lambda x: -x[1][0]):
         lines.append(f"| {st} | {c} | {ns / 1e6:.3f} | {ns / c / 1e3:.1f} |")
@@ -348,7 +358,8 @@ def summarize_profiles(d, workload, cfg):
             if st:
                 a = per.setdefault(st, [0.0, 0])
                 a[0] += kib
-                a[1] += 1
+                if not _is_second(r["Kernel_Name"]):
+                    a[1] += 1
         return per, probe
     fetch, fprobe = counter("fetch", "FETCH_SIZE")
     write, wprobe = counter("write", "WRITE_SIZE")
