@@ -354,7 +354,7 @@ int grid_size(int k, int pw, int tile, int stage) {
     per = std::min(8, zs::stage_blocks_per_cu(k, pw, tile, stage));
     cache[key] = per;
   }
-  if (stage == zs::STAGE_FINALIZE) return std::max(1, g_cu_count);
+  if (stage == zs::STAGE_FINALIZE) return std::max(1, g_cu_count) * 4;
   return std::max(1, g_cu_count) * per;
 }
 

@@ -146,23 +146,25 @@ __device__ __forceinline__ W8 w8_zero() {
   return r;
 }
 
-// r += v * 2^(32*pos) for a 64-bit v
+// r += v * 2^(32*pos) for a 64-bit v.  Every loop below runs its full
+// length with constant limb indices, so the numbers stay in registers.
 __device__ __forceinline__ void w8_add64_at(W8& r, uint64_t v, int pos) {
   uint64_t carry = 0;
-  for (int i = pos; i < 8; ++i) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
     uint64_t add = carry;
     if (i == pos) add += (uint32_t)v;
     if (i == pos + 1) add += (uint32_t)(v >> 32);
-    uint64_t s = (uint64_t)r.d[i] + add;
+    const uint64_t s = (uint64_t)r.d[i] + add;
     r.d[i] = (uint32_t)s;
     carry = s >> 32;
-    if (i > pos + 1 && carry == 0) break;
   }
 }
 
 __device__ __forceinline__ W8 w8_add(const W8& a, const W8& b) {
   W8 r;
   uint64_t c = 0;
+#pragma unroll
   for (int i = 0; i < 8; ++i) {
     uint64_t s = (uint64_t)a.d[i] + b.d[i] + c;
     r.d[i] = (uint32_t)s;
@@ -175,6 +177,7 @@ __device__ __forceinline__ W8 w8_add(const W8& a, const W8& b) {
 __device__ __forceinline__ W8 w8_sub(const W8& a, const W8& b) {
   W8 r;
   int64_t br = 0;
+#pragma unroll
   for (int i = 0; i < 8; ++i) {
     int64_t s = (int64_t)a.d[i] - (int64_t)b.d[i] - br;
     br = s < 0 ? 1 : 0;
@@ -186,9 +189,10 @@ __device__ __forceinline__ W8 w8_sub(const W8& a, const W8& b) {
 // full product of two numbers given as limb arrays (results must fit)
 __device__ __forceinline__ W8 w8_mul(const W8& a, const W8& b) {
   W8 r = w8_zero();
+#pragma unroll
   for (int i = 0; i < 8; ++i) {
-    if (a.d[i] == 0) continue;
     uint64_t carry = 0;
+#pragma unroll
     for (int j = 0; i + j < 8; ++j) {
       uint64_t t = (uint64_t)a.d[i] * b.d[j] + r.d[i + j] + carry;
       r.d[i + j] = (uint32_t)t;
@@ -545,15 +549,22 @@ __device__ void trace_ident(Ws& ws, const Seg& s) {
   r.shift = 0; r.nonempty = 0; r.hist_off = -1;
 }
 
+// statistics of the call that finalize() counts; the caller adds them to the
+// control block once per wave (one atomic per segment on one address would
+// queue up behind each other)
+struct FinStat {
+  uint64_t mkeys = 0;
+  uint32_t ident = 0, rmap = 0;
+};
+
 // acc: the segment's 32-bit digit sums a0..a5 (of x^2), b0, b1 (of x), then min, max
-__device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10]) {
-  Ctl* c = ws.ctl;
+__device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10], FinStat& fs) {
   const uint64_t cnt = s.count;
   const uint64_t o = acc[8];
   const uint64_t M = acc[9];
   s.o = o;
   s.M = M;
-  atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)cnt);
+  fs.mkeys += cnt;
 
   // raw sums: S1' = b0 + b1*2^32 ; S2' = a0 + a1*2^32 + a2*2^33 + a3*2^65 + a4*2^64 + a5*2^96
   W8 s1r = w8_zero();
@@ -580,7 +591,7 @@ __device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10]) {
 
   if (o == M) {  // all keys identical: solved, input order kept
     s.kind = KIND_IDENT;
-    atomicAdd(&c->n_ident, 1u);
+    ++fs.ident;
     trace_ident(ws, s);
     if (L & 1) {  // keys sit in the alternate buffer: copy them home, in parallel pieces
       for (uint64_t a = 0; a < s.count; a += (uint64_t)kCopyChunk)
@@ -622,7 +633,7 @@ __device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10]) {
     s.shift = bl > ws.p.lb ? bl - ws.p.lb : 0;
     s.kind = KIND_RMAP;
     s.flags |= F_RMAP;
-    atomicAdd(&c->n_rmap, 1u);
+    ++fs.rmap;
   } else {
     s.shift = 0;
     s.kind = KIND_ZMAP;
@@ -692,42 +703,92 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
 
 // finalize: one workgroup per segment sums the partial moments of its chunks
 // (exact, order-free integer sums), then one thread derives the statistics
-__global__ void __launch_bounds__(kBlock) k_finalize(Ws ws, int L) {
+constexpr int kFinThreads = kBlock;  // workgroup of the finalize kernel
+constexpr uint32_t kFinBig = 256;   // segments with more chunks are summed by a whole workgroup
+
+// sums of partials [q0, q1) with stride `step`, two chunks in flight per lane
+__device__ __forceinline__ void sum_partials(const uint64_t* part, uint32_t q0, uint32_t q1,
+                                             uint32_t step, uint64_t (&v)[10]) {
+  uint32_t q = q0;
+  for (; q + step < q1; q += 2 * step) {
+    uint64_t t[2][10];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int j = 0; j < 10; ++j) t[u][j] = part[(uint64_t)(q + u * step) * 10 + j];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] += t[u][j];
+      v[8] = t[u][8] < v[8] ? t[u][8] : v[8];
+      v[9] = t[u][9] > v[9] ? t[u][9] : v[9];
+    }
+  }
+  for (; q < q1; q += step) {
+    const uint64_t* pr = part + (uint64_t)q * 10;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] += pr[j];
+    v[8] = pr[8] < v[8] ? pr[8] : v[8];
+    v[9] = pr[9] > v[9] ? pr[9] : v[9];
+  }
+}
+
+__device__ __forceinline__ void wave_reduce_partials(uint64_t (&v)[10]) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] += __shfl_xor(v[j], o);
+    const uint64_t a = __shfl_xor(v[8], o), b = __shfl_xor(v[9], o);
+    v[8] = a < v[8] ? a : v[8];
+    v[9] = b > v[9] ? b : v[9];
+  }
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
   const int S = L & 1;
   const uint32_t ns = min(c->nseg[S], ws.seg_cap);
-  __shared__ uint64_t red[kWaves][10];
+  constexpr int NWV = kFinThreads / kWave;
+  __shared__ uint64_t red[NWV][10];
+  const uint32_t ln = lane(), wv = wave();
+  FinStat fs;
+  // segments of many chunks: a whole workgroup each
   for (uint32_t i = blockIdx.x; i < ns; i += gridDim.x) {
     Seg& sg = ws.segs[S][i];
+    if (sg.nchunks < kFinBig) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
-    for (uint32_t q = threadIdx.x; q < sg.nchunks; q += kBlock) {
-      const uint64_t* pr = ws.part + (uint64_t)(sg.first_work + q) * 10;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] += pr[j];
-      v[8] = pr[8] < v[8] ? pr[8] : v[8];
-      v[9] = pr[9] > v[9] ? pr[9] : v[9];
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] += __shfl_xor(v[j], o);
-      const uint64_t a = __shfl_xor(v[8], o), b = __shfl_xor(v[9], o);
-      v[8] = a < v[8] ? a : v[8];
-      v[9] = b > v[9] ? b : v[9];
-    }
-    if (lane() == 0)
-      for (int j = 0; j < 10; ++j) red[wave()][j] = v[j];
+    sum_partials(ws.part + (uint64_t)sg.first_work * 10, threadIdx.x, sg.nchunks, kFinThreads, v);
+    wave_reduce_partials(v);
+    if (ln == 0)
+      for (int j = 0; j < 10; ++j) red[wv][j] = v[j];
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int wv = 1; wv < kWaves; ++wv) {
-        for (int j = 0; j < 8; ++j) v[j] += red[wv][j];
-        v[8] = red[wv][8] < v[8] ? red[wv][8] : v[8];
-        v[9] = red[wv][9] > v[9] ? red[wv][9] : v[9];
+      for (int q = 1; q < NWV; ++q) {
+        for (int j = 0; j < 8; ++j) v[j] += red[q][j];
+        v[8] = red[q][8] < v[8] ? red[q][8] : v[8];
+        v[9] = red[q][9] > v[9] ? red[q][9] : v[9];
       }
-      finalize(ws, sg, L, v);
+      finalize(ws, sg, L, v, fs);
     }
     __syncthreads();
+  }
+  // the others: one wave each, whose lanes sum the chunk partials and whose
+  // lane 0 computes the statistics (waves of a workgroup work on different
+  // segments)
+  const uint32_t nwv = gridDim.x * NWV;
+  for (uint32_t i = blockIdx.x * NWV + wv; i < ns; i += nwv) {
+    Seg& sg = ws.segs[S][i];
+    if (sg.nchunks >= kFinBig) continue;
+    uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
+    sum_partials(ws.part + (uint64_t)sg.first_work * 10, ln, sg.nchunks, kWave, v);
+    wave_reduce_partials(v);
+    if (ln == 0) finalize(ws, sg, L, v, fs);
+  }
+  if (ln == 0) {
+    if (fs.mkeys) atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)fs.mkeys);
+    if (fs.ident) atomicAdd(&c->n_ident, fs.ident);
+    if (fs.rmap) atomicAdd(&c->n_rmap, fs.rmap);
   }
 }
 
@@ -747,6 +808,10 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t sh[kWaves + 2];
   uint32_t w;
   uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid;
+  // statistics of this workgroup's segments, added to the control block at
+  // the end of the kernel
+  unsigned long long st_keys;
+  uint32_t st_segs, st_groups;
 };
 
 template <int KMAX>
@@ -919,7 +984,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     sm.base_leaf = nsmall ? atomicAdd(&c->nleafw[S], nsmall) : 0u;
     sm.base_mid = nmid ? atomicAdd(&c->nleafm[S], nmid) : 0u;
     sm.base_status = nbig ? atomicAdd(&c->nleaf[S], nbig) : 0u;  // (reused as the big-list base)
-    if (nsmall + nmid + nbig) atomicAdd(&c->n_leafgroups, nsmall + nmid + nbig);
+    sm.st_groups += nsmall + nmid + nbig;
     if (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
         sm.base_status + nbig > ws.leaf_cap)
       atomicOr(&c->error, ERR_LEAFCAP);
@@ -956,8 +1021,8 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
 
   // statistics and trace
   if (t == 0) {
-    atomicAdd((unsigned long long*)&c->lvl_keys[L], (unsigned long long)sg.count);
-    atomicAdd(&c->lvl_segs[L], 1u);
+    sm.st_keys += sg.count;
+    sm.st_segs += 1u;
   }
   if (ws.trace) {
     uint32_t ne = 0;
@@ -1020,6 +1085,11 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   // tiles of the scatter per work item, each with its own starts (8192-key
   // tiles only, at most 4)
   const uint32_t nsub = tiles_per_item(ws);
+  if (t == 0) {
+    sm.st_keys = 0;
+    sm.st_segs = 0;
+    sm.st_groups = 0;
+  }
 
   while (true) {
     if (t == 0) sm.w = atomicAdd(&c->tick[L], 1u);
@@ -1121,6 +1191,11 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     __syncthreads();
     if (ci == nch - 1) classify<KMAX>(ws, sm, sg, si, L);
     __syncthreads();
+  }
+  if (t == 0) {
+    if (sm.st_keys) atomicAdd((unsigned long long*)&c->lvl_keys[L], sm.st_keys);
+    if (sm.st_segs) atomicAdd(&c->lvl_segs[L], sm.st_segs);
+    if (sm.st_groups) atomicAdd(&c->n_leafgroups, sm.st_groups);
   }
 }
 
@@ -2067,7 +2142,7 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       hipLaunchKernelGGL(k_moments, dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_FINALIZE:
-      hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, st, ws, L);
+      hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kFinThreads), 0, st, ws, L);
       break;
     case STAGE_HIST:
       if (ws.lm.ids && ws.lm.direct)
