@@ -64,7 +64,8 @@ enum {
  *                [2048, 2^20] (and of tile).  Default 16384.
  *   tile         keys a workgroup ranks per step of the stable scatter:
  *                2048, 4096 (256 threads) or 8192 (1024 threads); above 2048
- *                needs k <= 1024 and chunk a multiple of tile.  Default 2048.
+ *                needs k <= 1024 and chunk a multiple of tile; 8192 needs
+ *                chunk <= 65536.  Default 2048.
  *   flags        ZSORT_FLAG_GRAPH: run the whole sort as one cached hipGraph
  *                (every level of the recursion is launched; kernels of empty
  *                levels exit at once).  The graph is captured on a private

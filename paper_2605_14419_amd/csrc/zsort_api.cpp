@@ -232,7 +232,7 @@ int check_cfg(const zsort_config* c) {
   if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
   if (c->tile != 2048 && c->tile != 4096 && c->tile != 8192) return ZSORT_EINVAL;
   if (c->tile > 2048 && (c->k > 1024 || c->chunk % c->tile)) return ZSORT_EINVAL;
-  if (c->tile == 8192 && c->chunk > 32768) return ZSORT_EINVAL;
+  if (c->tile == 8192 && c->chunk > 65536) return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 

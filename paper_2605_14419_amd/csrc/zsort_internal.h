@@ -188,7 +188,7 @@ struct Ws {
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
   uint16_t* subpre;      // 8192-key tiles: each cluster's count in a work item before
                          // the tile that starts at key position p, row p >> 13, [row][k]
-  uint64_t* tiles[2];    // 8192-key tiles: (segment << 32) | (chunk << 2) | tile, the scatter's items
+  uint64_t* tiles[2];    // 8192-key tiles: (segment << 32) | (chunk << 3) | tile, the scatter's items
   Ctl* ctl;
   TraceRec* trace;       // may be null
   uint32_t* trace_hist;

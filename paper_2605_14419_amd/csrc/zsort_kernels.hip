@@ -398,9 +398,9 @@ __device__ __forceinline__ uint32_t tiles_per_item(const Ws& ws) {
   return ws.p.tile == 8192 ? (uint32_t)((uint32_t)ws.p.chunk >> 13) : 1u;
 }
 
-// tile u of segment si: (segment << 32) | (chunk << 2) | tile in the chunk
+// tile u of segment si: (segment << 32) | (chunk << 3) | tile in the chunk
 __device__ __forceinline__ uint64_t tile_entry(uint32_t si, uint32_t u, uint32_t nsub) {
-  return ((uint64_t)si << 32) | ((u / nsub) << 2) | (u % nsub);
+  return ((uint64_t)si << 32) | ((u / nsub) << 3) | (u % nsub);
 }
 
 __device__ void make_root_seg(Ws& ws, uint32_t slot_seg, uint64_t start, uint64_t count,
@@ -801,6 +801,7 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t h[KMAX];       // histogram, later totals (8192-key tiles: 16-bit counts of
                           // tiles 0 and 1 of the work item until the totals are formed)
   uint32_t hq[KMAX <= 1024 ? KMAX : 1];   // 16-bit counts of tiles 2 and 3
+  uint32_t hq2[KMAX <= 1024 ? 2 : 1][KMAX <= 1024 ? KMAX : 1];  // tiles 4, 5 and 6, 7
   uint32_t bst[KMAX];     // exclusive starts
   uint32_t t0[KMAX];      // scratch arrays for classification
   uint32_t t1[KMAX];
@@ -1062,8 +1063,9 @@ __device__ __forceinline__ void hist_add(HistSmem<KMAX>& sm, uint32_t b, uint64_
   if (KMAX > 1024 || nsub == 1) {
     atomicAdd(&sm.h[b], 1u);
   } else {
-    const uint32_t tile = (uint32_t)(off >> 13);
-    atomicAdd((tile & 2u) ? &sm.hq[b] : &sm.h[b], (tile & 1u) ? 0x10000u : 1u);
+    const uint32_t tile = (uint32_t)(off >> 13), wd = tile >> 1;
+    uint32_t* a = wd == 0 ? &sm.h[b] : (wd == 1 ? &sm.hq[b] : &sm.hq2[(wd - 2) & 1][b]);
+    atomicAdd(a, (tile & 1u) ? 0x10000u : 1u);
   }
 }
 
@@ -1083,7 +1085,7 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   const uint32_t tag = level_tag(c->epoch, L);
   const int t = threadIdx.x;
   // tiles of the scatter per work item, each with its own starts (8192-key
-  // tiles only, at most 4)
+  // tiles only, at most 8)
   const uint32_t nsub = tiles_per_item(ws);
   if (t == 0) {
     sm.st_keys = 0;
@@ -1106,7 +1108,10 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     for (int b = t; b < k; b += kBlock) {
       sm.h[b] = 0;
-      if constexpr (KMAX <= 1024) sm.hq[b] = 0;
+      if constexpr (KMAX <= 1024) {
+        sm.hq[b] = 0;
+        if (nsub > 4) sm.hq2[0][b] = sm.hq2[1][b] = 0;
+      }
     }
     __syncthreads();
     if constexpr (LM != 0) {
@@ -1141,10 +1146,12 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
       // each cluster's count before it (the scatter's start inside the item)
       for (int b = t; b < k; b += kBlock) {
         const uint32_t v0 = sm.h[b], v1 = sm.hq[b];
-        const uint32_t cnt[4] = {v0 & 0xFFFFu, v0 >> 16, v1 & 0xFFFFu, v1 >> 16};
+        const uint32_t v2 = nsub > 4 ? sm.hq2[0][b] : 0u, v3 = nsub > 4 ? sm.hq2[1][b] : 0u;
+        const uint32_t cnt[8] = {v0 & 0xFFFFu, v0 >> 16, v1 & 0xFFFFu, v1 >> 16,
+                                 v2 & 0xFFFFu, v2 >> 16, v3 & 0xFFFFu, v3 >> 16};
         uint32_t run = cnt[0];
 #pragma unroll
-        for (uint32_t q = 1; q < 4; ++q) {
+        for (uint32_t q = 1; q < 8; ++q) {
           if (q < nsub) {
             const uint64_t p = beg + ((uint64_t)q << 13);
             if (p < end) ws.subpre[(p >> 13) * (uint64_t)k + b] = (uint16_t)run;
@@ -1274,8 +1281,8 @@ __global__ void __launch_bounds__(SB, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, in
     if (nsub > 1) {
       const uint64_t e = ws.tiles[S][wt];
       si = (uint32_t)(e >> 32);
-      ci = (uint32_t)e >> 2;
-      sub = (uint32_t)e & 3u;
+      ci = (uint32_t)e >> 3;
+      sub = (uint32_t)e & 7u;
     } else {
       const uint64_t item = ws.work[S][wt];
       si = (uint32_t)(item >> 32);

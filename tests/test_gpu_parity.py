@@ -246,7 +246,7 @@ def test_full_size_bench_configuration(name, pw):
     check_stable_sorted(x, k, p)
 
 
-@pytest.mark.parametrize("chunk", [8192, 16384])
+@pytest.mark.parametrize("chunk", [8192, 16384, 65536])
 def test_segmented_tile8192_vs_oracle(chunk):
     """8192-key tiles as work items of their own (one, two per chunk) across
     many segments, each segment's starts taken from the histogram pass"""
@@ -260,3 +260,17 @@ def test_segmented_tile8192_vs_oracle(chunk):
     k, p = from_dev(tk, tp)
     ok, oi = oracle.sort_segmented(keys, off, idx, k=512, cutoff=512, max_zlevels=8)
     assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
+@pytest.mark.parametrize("k,pw", [(256, 8), (1024, 4)])
+def test_eight_tiles_per_work_item_vs_oracle(k, pw):
+    """chunks of 65536 keys: each work item has eight 8192-key tiles whose
+    starts come from the histogram pass's per-tile counts"""
+    n = 2 * 65536 + 12_345
+    x, pay = synth.make("lognormal", n, payload_bytes=pw)
+    cfg = dict(k=k, cutoff=256, max_zlevels=8, chunk=65536, tile=8192)
+    say(f"case eight tiles {cfg} pw={pw}")
+    kk, p, st = gpu_sort(x, pay, cfg)
+    assert st["device_error"] == 0, st
+    ok, op, _ = oracle.sort(x, pay, k=k, cutoff=256, max_zlevels=8)
+    assert np.array_equal(kk, ok) and np.array_equal(p, op)
