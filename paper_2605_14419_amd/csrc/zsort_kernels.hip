@@ -42,13 +42,57 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
   return m;
 }
 
+// Inclusive sum over the wave by DPP moves (all 64 lanes active): shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes (lanes before the row start read
+// 0), then the last lane of row 0 is added to row 1 and that of row 2 to
+// row 3 (row_bcast:15), and the last lane of row 1 to rows 2 and 3
+// (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t t = __shfl_up(v, o);
-    if (lane() >= (uint32_t)o) v += t;
-  }
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
   return v;
+}
+
+// 64-bit value of the DPP source lane (CTRL, ROWS as above), `idv` where the
+// lane has no source
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t idv, uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)idv, (int)(uint32_t)v,
+                                                             CTRL, ROWS, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(idv >> 32),
+                                                             (int)(uint32_t)(v >> 32), CTRL, ROWS,
+                                                             0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// minimum and maximum over the wave (all 64 lanes active), the same DPP
+// pattern as wave_incl_sum; the last lane holds the result, read by all
+__device__ __forceinline__ void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
+  uint64_t a, b;
+#define ZS_MM_STEP(CTRL, ROWS)                        \
+  a = dpp64<CTRL, ROWS>(~0ull, mn);                   \
+  b = dpp64<CTRL, ROWS>(0ull, mx);                    \
+  mn = a < mn ? a : mn;                               \
+  mx = b > mx ? b : mx;
+  ZS_MM_STEP(0x111, 0xF)
+  ZS_MM_STEP(0x112, 0xF)
+  ZS_MM_STEP(0x114, 0xF)
+  ZS_MM_STEP(0x118, 0xF)
+  ZS_MM_STEP(0x142, 0xA)
+  ZS_MM_STEP(0x143, 0xC)
+#undef ZS_MM_STEP
+  mn = readlane64(mn, kWave - 1);
+  mx = readlane64(mx, kWave - 1);
 }
 
 __device__ __forceinline__ int wave_incl_max(int v) {
@@ -1819,12 +1863,7 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
       if constexpr (PW != 0) pb[i] = pay[r];
     }
   }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
+  wave_minmax_u64(mn, mx);
   if constexpr (TW > 1) {
     if (ln == 0) { rmin[tw] = mn; rmax[tw] = mx; }
     team_sync<TW>();
@@ -1879,20 +1918,19 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
     }
   }
   uint32_t base;
-  uint32_t gmax = tmax;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, o));
+  // some bucket above kBucketMax keys (a ballot per wave)
+  uint32_t big = __ballot(tmax > (uint32_t)kBucketMax) != 0ull ? 1u : 0u;
   if constexpr (TW == 1) {
     base = wave_incl_sum(tsum) - tsum;
   } else {
-    if (ln == 0) sh[tw] = gmax;
+    if (ln == 0) sh[tw] = big;
     team_sync<TW>();
-    for (int q = 0; q < TW; ++q) gmax = max(gmax, sh[q]);
+    for (int q = 0; q < TW; ++q) big |= sh[q];
     team_sync<TW>();
     uint32_t total;
     base = block_excl_sum(tsum, sh, &total);
   }
-  if (gmax > (uint32_t)kBucketMax) {
+  if (big) {
     team_sync<TW>();
     return false;
   }
