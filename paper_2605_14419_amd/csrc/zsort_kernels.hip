@@ -95,6 +95,28 @@ __device__ __forceinline__ void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
   mx = readlane64(mx, kWave - 1);
 }
 
+// the ten moment words of every lane reduced over the wave (sums of the
+// first eight, min and max of the last two), the result in every lane
+__device__ __forceinline__ void wave_reduce_moments(uint64_t (&v)[10]) {
+#define ZS_RM_STEP(CTRL, ROWS)                                      \
+  {                                                                 \
+    _Pragma("unroll") for (int j = 0; j < 8; ++j) v[j] += dpp64<CTRL, ROWS>(0ull, v[j]); \
+    const uint64_t a = dpp64<CTRL, ROWS>(~0ull, v[8]);             \
+    const uint64_t b = dpp64<CTRL, ROWS>(0ull, v[9]);              \
+    v[8] = a < v[8] ? a : v[8];                                     \
+    v[9] = b > v[9] ? b : v[9];                                     \
+  }
+  ZS_RM_STEP(0x111, 0xF)
+  ZS_RM_STEP(0x112, 0xF)
+  ZS_RM_STEP(0x114, 0xF)
+  ZS_RM_STEP(0x118, 0xF)
+  ZS_RM_STEP(0x142, 0xA)
+  ZS_RM_STEP(0x143, 0xC)
+#undef ZS_RM_STEP
+#pragma unroll
+  for (int j = 0; j < 10; ++j) v[j] = readlane64(v[j], kWave - 1);
+}
+
 __device__ __forceinline__ int wave_incl_max(int v) {
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
@@ -721,14 +743,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
     });
     uint64_t vals[10] = {a0, a1, a2, a3, a4, a5, b0, b1, mn, mx};
     (void)sg;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) vals[j] += __shfl_xor(vals[j], o);
-      uint64_t tmn = __shfl_xor(vals[8], o), tmx = __shfl_xor(vals[9], o);
-      vals[8] = tmn < vals[8] ? tmn : vals[8];
-      vals[9] = tmx > vals[9] ? tmx : vals[9];
-    }
+    wave_reduce_moments(vals);
     if (lane() == 0)
       for (int j = 0; j < 10; ++j) red[wave()][j] = vals[j];
     __syncthreads();
@@ -777,16 +792,6 @@ __device__ __forceinline__ void sum_partials(const uint64_t* part, uint32_t q0, 
   }
 }
 
-__device__ __forceinline__ void wave_reduce_partials(uint64_t (&v)[10]) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] += __shfl_xor(v[j], o);
-    const uint64_t a = __shfl_xor(v[8], o), b = __shfl_xor(v[9], o);
-    v[8] = a < v[8] ? a : v[8];
-    v[9] = b > v[9] ? b : v[9];
-  }
-}
 
 __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   Ctl* c = ws.ctl;
@@ -803,7 +808,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
     if (sg.nchunks < kFinBig) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
     sum_partials(ws.part + (uint64_t)sg.first_work * 10, threadIdx.x, sg.nchunks, kFinThreads, v);
-    wave_reduce_partials(v);
+    wave_reduce_moments(v);
     if (ln == 0)
       for (int j = 0; j < 10; ++j) red[wv][j] = v[j];
     __syncthreads();
@@ -826,7 +831,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
     if (sg.nchunks >= kFinBig) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
     sum_partials(ws.part + (uint64_t)sg.first_work * 10, ln, sg.nchunks, kWave, v);
-    wave_reduce_partials(v);
+    wave_reduce_moments(v);
     if (ln == 0) finalize(ws, sg, L, v, fs);
   }
   if (ln == 0) {
