@@ -114,15 +114,21 @@ def run_workload(spec, steps, warmup, cfg, dev, profile=True):
         zs.zsort_profile_begin()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     ev0.record()
     for i in range(steps):
+        evs[i].record()
         zs.zsort_stable_ex(ins[i][0], ins[i][1], cfg)
+    evs[steps].record()
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    med = per_step[steps // 2] if steps % 2 else 0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2])
     kt = zs.zsort_profile_end() if profile else None
     stats = zs.zsort_get_last_stats()
+    stats["ms_per_step_median"] = med
     assert stats["device_error"] == 0, stats
     verify_on_device(base_k, ins[-1][0], ins[-1][1])
     log(f"[bench] {spec['workload']}: {ms:.3f} ms/step, levels {stats['levels']}, verified")
@@ -372,8 +378,9 @@ def summarize_profiles(d, workload, cfg):
              f"Copy probe (1 GiB read, 1 GiB written per copy): FETCH_SIZE reads "
              f"{sum(fprobe) / len(fprobe) / 1024:.1f} MiB -> factor {ff:.3f}; WRITE_SIZE reads "
              f"{sum(wprobe) / len(wprobe) / 1024:.1f} MiB -> factor {wf:.3f}.", "",
-             "| stage | launches | fetch MB/launch (scaled) | write MB/launch (scaled) | total MB/launch |",
-             "|---|---|---|---|---|"]
+             "| stage | launches | fetch MB/launch (scaled) | write MB/launch (scaled) | total MB/launch "
+             "| avg launch us (kernel trace) | traffic GB/s |",
+             "|---|---|---|---|---|---|---|"]
     traffic = {}
     for st in STAGES:
         if st not in fetch or st not in write:
@@ -381,7 +388,10 @@ def summarize_profiles(d, workload, cfg):
         fb = fetch[st][0] / fetch[st][1] * 1024 * ff
         wb = write[st][0] / write[st][1] * 1024 * wf
         traffic[st] = fb + wb
-        lines.append(f"| {st} | {fetch[st][1]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+        us = per_stage[st][0] / per_stage[st][1] / 1e3 if st in per_stage else 0.0
+        gbs = (fb + wb) / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        lines.append(f"| {st} | {fetch[st][1]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} "
+                     f"| {us:.1f} | {gbs:.0f} |")
     with open(os.path.join(out_dir, f"traffic_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     dom = max(per_stage, key=lambda s: per_stage[s][0])
@@ -391,6 +401,58 @@ def summarize_profiles(d, workload, cfg):
                    "per_stage_bytes_per_launch": {k: round(v) for k, v in traffic.items()},
                    "fetch_factor": ff, "write_factor": wf}, fh, indent=1)
     print(f"wrote kernels_{workload}.md, traffic_{workload}.md/.json (dominant {dom})")
+
+
+def measured_copy_gbs(dev, reps=5):
+    """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
+    (1 GiB read + 1 GiB written), median of `reps`, in GB/s of read + write."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.int64, device=dev).fill_(3)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    t = sorted(times)[reps // 2]
+    return round(2 * (1 << 30) / (t * 1e-3) / 1e9, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_library_reference(keys, budget_s=3.0):
+    """numpy's stable argsort (a library sort, not the method) on the same
+    sample, single-threaded: context for the oracle's number."""
+    ns = min(keys.size, 10**7)
+    sample = np.ascontiguousarray(keys[:ns])
+    reps, t0 = 0, time.time()
+    while True:
+        order = np.argsort(sample, kind="stable")
+        sample[order]
+        reps += 1
+        el = time.time() - t0
+        if el >= budget_s or reps >= 10:
+            break
+    return {"value": round(ns * reps / el / 1e9, 5), "unit": "GKeys/s", "cores": 1,
+            "kind": "numpy argsort(kind='stable') + gather",
+            "sample": f"first {ns} keys of the same array, {reps} rep(s)"}
 
 
 def cpu_baseline(keys, cfg, budget_s):
@@ -406,7 +468,7 @@ def cpu_baseline(keys, cfg, budget_s):
         if el >= budget_s or reps >= 20:
             break
     return {"value": round(ns * reps / el / 1e9, 5), "unit": "GKeys/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {ns} keys of the same array, u32 index payload, {reps} rep(s), "
                       f"{el:.1f}s single-threaded"}
 
@@ -459,6 +521,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies")
+    copy_gbs = measured_copy_gbs(dev)
+    log(f"[bench] measured copy bandwidth {copy_gbs} GB/s (read + write)")
     fixed = None
     if args.config:
         fixed = dict(DEFAULT_CFG)
@@ -481,7 +545,11 @@ def main():
         "hbm_frac_effective": round(model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_frac_sort_equivalent": round(2 * (8 + pw) * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "model_bytes_per_step": model,
+        "ms_per_step_median": round(stats["ms_per_step_median"], 4),
+        "hbm": {"peak_gbs": HBM_PEAK_GBS, "measured_copy_gbs": copy_gbs,
+                "effective_frac_of_copy": round(model / (ms * 1e-3) / 1e9 / copy_gbs, 4)},
         "levels": stats["levels"],
+        "keys_per_level": stats.get("keys_per_level"),
         "kernel_ms_per_step": {s: round(kt[s][0] / args.steps, 4) for s in STAGES},
         "roofline": rl,
     }
@@ -516,6 +584,7 @@ def main():
     out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(keys, cfg, args.cpu_budget)
+        out["cpu_library_reference"] = cpu_library_reference(keys)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
