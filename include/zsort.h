@@ -74,8 +74,15 @@ enum {
  *                Without the flag the library launches level by level and
  *                stops one level after the recursion ends, waiting on the
  *                device's progress between levels (host-side pacing).
+ *                ZSORT_FLAG_SIGNED: the keys are two's-complement int64 and
+ *                are ordered as signed numbers (the sign bit is flipped in
+ *                place before the sort and back after it: two more passes
+ *                over the keys).  zsort_stable_ex and zsort_stable_segmented
+ *                only; the debug, traced and learned entry points return
+ *                ZSORT_EUNSUPPORTED for it.
  */
 #define ZSORT_FLAG_GRAPH 1
+#define ZSORT_FLAG_SIGNED 2
 typedef struct zsort_config {
   int32_t k;
   int32_t cutoff;
@@ -280,7 +287,7 @@ int zsort_profile_end(void* stream, zsort_kernel_times* out /* host */);
  * The output is the same stable sort in every case.
  *
  * The call is synchronous (it waits for the check).  cfg as for
- * zsort_stable_ex (ZSORT_FLAG_GRAPH is not supported); lcfg may be NULL
+ * zsort_stable_ex (ZSORT_FLAG_GRAPH and ZSORT_FLAG_SIGNED are not supported); lcfg may be NULL
  * (defaults); report (host) may be NULL.  Arrays too small for a first pass
  * (n <= cutoff) or for a sample of 64 keys take the plain path
  * (report->used_learned = 0, report->fallback = 0).

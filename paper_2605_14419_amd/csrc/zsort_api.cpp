@@ -18,6 +18,7 @@
 
 namespace zs {
 hipError_t launch_reset(const Ws& ws, hipStream_t st);
+hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st);
 hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st);
 hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, uint64_t n,
                                 hipStream_t st);
@@ -142,10 +143,11 @@ struct GraphKey {
   const void* off;
   uint64_t n;
   int32_t nseg;
-  int pw, k, cutoff, maxz, chunk, tile;
+  int pw, k, cutoff, maxz, chunk, tile, flags;
   bool operator<(const GraphKey& o) const {
-    return std::tie(keys, pay, off, n, nseg, pw, k, cutoff, maxz, chunk, tile) <
-           std::tie(o.keys, o.pay, o.off, o.n, o.nseg, o.pw, o.k, o.cutoff, o.maxz, o.chunk, o.tile);
+    return std::tie(keys, pay, off, n, nseg, pw, k, cutoff, maxz, chunk, tile, flags) <
+           std::tie(o.keys, o.pay, o.off, o.n, o.nseg, o.pw, o.k, o.cutoff, o.maxz, o.chunk, o.tile,
+                    o.flags);
   }
 };
 
@@ -412,7 +414,7 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
                      !capturing(st);
   if (graph) {
     GraphKey gk{c.keys, c.pay, c.off, c.n, c.off ? c.nseg : 0, c.pw, c.cfg.k, c.cfg.cutoff,
-                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile};
+                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile, c.cfg.flags & ZSORT_FLAG_SIGNED};
     auto it = w->graphs.find(gk);
     hipGraphExec_t ex = nullptr;
     if (it != w->graphs.end()) {
@@ -454,15 +456,20 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
 
 hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0);
 
-// the launch sequence of one sort on stream st
+// the launch sequence of one sort on stream st (signed keys: the sign bit
+// is flipped before and after, so that the unsigned sort orders them)
 hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
-  hipError_t e = zs::launch_reset(ws, st);
+  const bool sgn = (c.cfg.flags & ZSORT_FLAG_SIGNED) != 0;
+  const int fgrid = std::max(1, g_cu_count) * 8;
+  hipError_t e = sgn ? zs::launch_flip(c.keys, c.n, fgrid, st) : hipSuccess;
+  if (e == hipSuccess) e = zs::launch_reset(ws, st);
   if (e == hipSuccess) {
     if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
     else e = zs::launch_init_single(ws, c.n, st);
   }
-  if (e != hipSuccess) return e;
-  return enqueue_levels(w, ws, c, st, 0);
+  if (e == hipSuccess) e = enqueue_levels(w, ws, c, st, 0);
+  if (e == hipSuccess && sgn) e = zs::launch_flip(c.keys, c.n, fgrid, st);
+  return e;
 }
 
 // levels L0, L0 + 1, ... (L0 > 0: level L0 - 1 ran already and recorded its
@@ -806,6 +813,7 @@ int zsort_debug_level0(const uint64_t* keys, const void* payload, int payload_by
   rc = resolve_cfg(cfg, &c);
   if (rc) return rc;
   if (n <= (size_t)c.cutoff || !out_keys || (payload_bytes && !out_payload)) return ZSORT_EINVAL;
+  if (c.flags & ZSORT_FLAG_SIGNED) return ZSORT_EUNSUPPORTED;
   std::lock_guard<std::mutex> lk(g_mu);
   hipStream_t st = (hipStream_t)stream;
   Call call{const_cast<uint64_t*>(keys), payload_bytes ? const_cast<void*>(payload) : nullptr,
@@ -835,6 +843,7 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
   if (trace_cap < 0 || hist_cap < 0 || (trace_cap && !trace) || (hist_cap && !hist) || !counts)
     return ZSORT_EINVAL;
   if (trace_cap > 0xFFFFFFF || hist_cap > 0xFFFFFFFF) return ZSORT_EINVAL;
+  if (c.flags & ZSORT_FLAG_SIGNED) return ZSORT_EUNSUPPORTED;
   counts[0] = counts[1] = 0;
   if (n <= 1) return ZSORT_OK;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -1036,7 +1045,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   zsort_config c;
   rc = resolve_cfg(cfg, &c, n, payload_bytes, 0);
   if (rc) return rc;
-  if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
+  if (c.flags & (ZSORT_FLAG_GRAPH | ZSORT_FLAG_SIGNED)) return ZSORT_EUNSUPPORTED;
   uint32_t* host_counts = report ? report->counts : nullptr;
   zsort_mlp_params* params_out = report ? report->params_out : nullptr;
   if (report) {

@@ -2221,6 +2221,18 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
 // entry points used by the host planner (zsort_api.cpp)
 namespace zs {
 
+// signed keys: two's complement order is the unsigned order of x ^ 2^63
+__global__ void __launch_bounds__(kBlock) k_flip(uint64_t* __restrict__ x, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    x[i] ^= 0x8000000000000000ull;
+}
+
+hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_flip, dim3(grid), dim3(kBlock), 0, st, keys, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(const Ws& ws, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, ws);
   return hipGetLastError();

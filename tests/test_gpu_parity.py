@@ -274,3 +274,57 @@ def test_eight_tiles_per_work_item_vs_oracle(k, pw):
     assert st["device_error"] == 0, st
     ok, op, _ = oracle.sort(x, pay, k=k, cutoff=256, max_zlevels=8)
     assert np.array_equal(kk, ok) and np.array_equal(p, op)
+
+
+SIGN = np.uint64(1 << 63)
+
+
+def signed_expected(x, idx, k, off=None):
+    """the oracle on the order-preserving map int64 -> u64 (flip the sign
+    bit), mapped back"""
+    xu = x ^ SIGN
+    if off is None:
+        ok, oi, _ = oracle.sort(xu, idx, k=k, cutoff=2048, max_zlevels=8)
+    else:
+        ok, oi = oracle.sort_segmented(xu, off, idx, k=k, cutoff=2048, max_zlevels=8)
+    return ok ^ SIGN, oi
+
+
+@pytest.mark.parametrize("name,flags", [("uniform", 2), ("normal", 2), ("dup_heavy", 3)])
+def test_signed_keys_vs_oracle(name, flags):
+    """ZSORT_FLAG_SIGNED: keys ordered as two's-complement int64 (with and
+    without the captured graph)"""
+    n = 300_007
+    x, idx = synth.make(name, n)
+    x = x - np.uint64(1 << 62)          # wraps: about a quarter negative as int64
+    cfg = dict(CFG, flags=flags)
+    say(f"case signed {name} flags={flags}")
+    for rep in range(2 if flags & 1 else 1):   # graph: capture, then replay
+        k, p, st = gpu_sort(x, idx, cfg)
+        assert st["device_error"] == 0, st
+        ek, ep = signed_expected(x, idx, 1024)
+        assert np.array_equal(k, ek) and np.array_equal(p, ep), rep
+    s = k.view(np.int64)
+    assert np.all(s[1:] >= s[:-1]) and s[0] < 0
+
+
+def test_signed_segmented_vs_oracle():
+    keys, off, idx = synth.segments(64, 33, median=5000, hi=50_000)
+    keys = keys ^ SIGN                   # the upper half of each array's range turns negative
+    say(f"case signed segmented n={keys.size}")
+    tk, tp = to_dev(keys, idx)
+    zs.zsort_stable_segmented(tk, torch.from_numpy(off).to(DEV), tp,
+                              dict(CFG, flags=zs.ZSORT_FLAG_SIGNED))
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] == 0
+    k, p = from_dev(tk, tp)
+    ek, ep = signed_expected(keys, idx, 1024, off)
+    assert np.array_equal(k, ek) and np.array_equal(p, ep)
+
+
+def test_signed_flag_rejected_where_unsupported():
+    x, idx = synth.make("uniform", 5000)
+    tk, tp = to_dev(x, idx)
+    with pytest.raises(zs.ZsortError) as ei:
+        zs.zsort_debug_level0(tk, tp, dict(CFG, flags=zs.ZSORT_FLAG_SIGNED))
+    assert ei.value.code == -5
