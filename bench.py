@@ -137,6 +137,43 @@ def run_workload(spec, steps, warmup, cfg, dev, profile=True):
     return keys, ms, stats, kt, cfg
 
 
+def run_alpha(dev, n=10**7, alphas=(0.2, 0.4, 0.6, 0.8, 1.0, 1.2), steps=3):
+    """The paper's sensitivity to k = alpha * sqrt(n) (its heuristics
+    paragraph finds alpha = 0.6 best on a CPU), here on the GPU: uniform u64
+    keys + u32 index at n = 10^7 (k up to 3795 clusters per pass, so 2048-key
+    tiles), k held for every level as the method holds it."""
+    import synth
+    import torch
+    import paper_2605_14419_amd as zs
+    keys, pay = synth.make("uniform", n, payload_bytes=4)
+    base_k, base_p = to_device(keys, pay, dev)
+    rows = []
+    for a in alphas:
+        k = int(round(a * n ** 0.5))
+        cfg = dict(k=k, cutoff=2048, max_zlevels=8, chunk=16384, tile=2048)
+        tk, tp = base_k.clone(), base_p.clone()
+        zs.zsort_stable_ex(tk, tp, cfg)
+        ins = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(steps):
+            zs.zsort_stable_ex(ins[i][0], ins[i][1], cfg)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = zs.zsort_get_last_stats()
+        assert st["device_error"] == 0, st
+        verify_on_device(base_k, ins[-1][0], ins[-1][1])
+        rows.append({"alpha": a, "k": k, "ms_per_step": round(ms, 4),
+                     "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3), "levels": st["levels"]})
+        del ins
+    log("[bench] alpha sweep: " + ", ".join(f"{r['alpha']}: {r['ms_per_step']:.3f} ms" for r in rows))
+    return {"workload": f"{n} uniform u64 keys, u32 index; k = alpha*sqrt(n), cutoff 2048, "
+                        "chunk 16384, 2048-key tiles", "rows": rows}
+
+
 def run_batched(steps, warmup, dev, nseg=4096):
     """Batched form: nseg arrays in one segmented call replayed as a cached
     hipGraph, against a loop of plain single-array calls (one per segment)."""
@@ -478,7 +515,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["learned", "batched"]),
+    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["learned", "batched", "alpha"]),
                     help="comma list, or 'none'")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -558,6 +595,9 @@ def main():
         for name in args.extras.split(","):
             if name == "batched":
                 extras[name] = run_batched(max(3, args.steps // 2), 1, dev)
+                continue
+            if name == "alpha":
+                extras[name] = run_alpha(dev)
                 continue
             if name == "learned":
                 extras[name] = run_learned(max(3, args.steps // 2), 1, dev)
