@@ -26,7 +26,11 @@ constexpr int kMaxLevels = 40;
 constexpr int kKMax = 4096;            // largest clusters-per-pass supported
 constexpr int kLocalCap = 4096;        // largest group the fallback local sort takes
 constexpr int kBlockCap = 2048;        // largest group (= largest cutoff) of the fast local sort
-constexpr int kWaveCap = 512;          // largest group one wave sorts
+constexpr int kWaveCap = 512;          // largest group one wave of the fallback sort takes
+// largest group one wave of the fast local sort takes (wave jobs): 10 keys
+// per lane with payloads of up to 4 bytes, 8 with 8-byte payloads (the LDS of
+// a workgroup holds four such groups)
+constexpr int wave_job_cap(int pw) { return pw == 8 ? 512 : 640; }
 constexpr int kMidCap = 1024;          // largest block job that one wave of k_local_mid sorts
 constexpr int kWindow = 256;           // leaf-group window; larger leaves sort alone
 constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
@@ -78,8 +82,8 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nseg[2];
   uint32_t nwork[2];
   uint32_t nleaf[2];             // block jobs: big leaves and copies
-  uint32_t nleafw[2];            // wave jobs: groups of <= kWaveCap keys
-  uint32_t nleafm[2];            // one-wave jobs of kWaveCap < n <= kMidCap keys
+  uint32_t nleafw[2];            // wave jobs: groups of <= wave_job_cap(pw) keys
+  uint32_t nleafm[2];            // one-wave jobs of wave_job_cap(pw) < n <= kMidCap keys
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
   uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list

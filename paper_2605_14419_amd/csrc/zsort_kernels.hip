@@ -439,11 +439,11 @@ __global__ void k_reset(Ws ws) {
 }
 
 // appends a sort job for keys [start, start+count) living in buffer `src`
-// of level-slot S: groups of <= kWaveCap keys go to the wave list
+// of level-slot S: groups of <= wave_job_cap(pw) keys go to the wave list
 __device__ bool push_leaf(Ws& ws, int S, uint64_t start, uint32_t count, uint32_t flags,
                           uint32_t src) {
   Ctl* c = ws.ctl;
-  const bool small = !(flags & LF_COPY) && count <= (uint32_t)kWaveCap;
+  const bool small = !(flags & LF_COPY) && count <= (uint32_t)wave_job_cap(ws.p.pw);
   const bool mid = !(flags & LF_COPY) && !small && count <= (uint32_t)kMidCap;
   uint32_t* ctr = small ? &c->nleafw[S] : (mid ? &c->nleafm[S] : &c->nleaf[S]);
   const uint32_t li = atomicAdd(ctr, 1u);
@@ -1017,12 +1017,13 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   for (int b = t; b < k; b += kBlock)
     if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
   __syncthreads();
+  const uint32_t wcap = (uint32_t)wave_job_cap(ws.p.pw);
   uint32_t my_small = 0, my_mid = 0, my_big = 0;
   for (uint32_t i = t; i < nb; i += kBlock) {
     if (!(bpos[i] >> 31)) continue;
     const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
     const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
-    if (p1 - p0 <= (uint32_t)kWaveCap) ++my_small;
+    if (p1 - p0 <= wcap) ++my_small;
     else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
     else ++my_big;
   }
@@ -1047,7 +1048,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
       const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
-      const bool small = p1 - p0 <= (uint32_t)kWaveCap;
+      const bool small = p1 - p0 <= wcap;
       const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
       Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
       lf.start = (uint32_t)(sg.start + p0);
@@ -1819,11 +1820,17 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
 // ---------------------------------------------------------------------------
 constexpr int kBucketMax = 16;
 
+constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2); }
+
 template <int PW>
 struct FastSmem {
-  uint64_t k[kBlockCap];                        // words in bucket order
-  typename PayT<PW>::T pay[PW ? kBlockCap : 1]; // payload by input position
-  uint32_t cnt[kBlockCap / 2];                  // 16-bit bucket counters, two per word
+  // block jobs use all of it; wave jobs a quarter each
+  static constexpr int KW = kBlockCap > kWaves * wave_job_cap(PW) ? kBlockCap : kWaves * wave_job_cap(PW);
+  static constexpr int CW = kBlockCap / 2 > kWaves * pow2_ceil(wave_job_cap(PW)) / 2
+                                ? kBlockCap / 2 : kWaves * pow2_ceil(wave_job_cap(PW)) / 2;
+  uint64_t k[KW];                               // words in bucket order
+  typename PayT<PW>::T pay[PW ? KW : 1];        // payload by input position
+  uint32_t cnt[CW];                             // 16-bit bucket counters, two per word
   uint64_t rmin[kWaves], rmax[kWaves];
   uint32_t sh[kWaves + 2];
 };
@@ -2016,7 +2023,21 @@ __device__ void push_hard(Ws& ws, int S, const Leaf& lf) {
 }
 
 template <int PW>
-__global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
+__device__ __forceinline__ void local_body(Ws ws, int L);
+
+// the local sort's kernel: with payloads of up to 4 bytes a wave job holds 10
+// keys per lane, and the register budget is pinned to four waves per SIMD
+template <int PW>
+__global__ void __launch_bounds__(kBlock, 4) k_local(Ws ws, int L) {
+  local_body<PW>(ws, L);
+}
+template <>
+__global__ void __launch_bounds__(kBlock) k_local<8>(Ws ws, int L) {
+  local_body<8>(ws, L);
+}
+
+template <int PW>
+__device__ __forceinline__ void local_body(Ws ws, int L) {
   using Sm = FastSmem<PW>;
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
@@ -2030,7 +2051,7 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   const int t = threadIdx.x;
   uint64_t moved = 0;  // keys this thread accounted for (statistics only)
 
-  // block jobs: copies of all-identical segments and groups of > kWaveCap keys
+  // block jobs: copies of all-identical segments and groups of > kMidCap keys
   for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
     const Leaf lf = ws.leaves[S][g];
     const uint64_t* __restrict__ src = ws.keys[lf.src];
@@ -2055,12 +2076,13 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
     if (!ok && t == 0) push_hard(ws, S, lf);
   }
   __syncthreads();
-  // wave jobs: groups of <= kWaveCap keys, one wave each
-  uint64_t* kb = sm.k + wv * kWaveCap;
-  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
-  uint32_t* cb = sm.cnt + wv * (kWaveCap / 2);
+  // wave jobs: groups of <= wave_job_cap(PW) keys, one wave each
+  constexpr int WCAP = wave_job_cap(PW);
+  uint64_t* kb = sm.k + wv * WCAP;
+  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * WCAP : 0);
+  uint32_t* cb = sm.cnt + wv * (pow2_ceil(WCAP) / 2);
   // the next group's keys and payloads are loaded while this one is sorted
-  constexpr int RW = kWaveCap / kWave;
+  constexpr int RW = WCAP / kWave;
   using P = typename PayT<PW>::T;
   const uint32_t gs = gridDim.x * kWaves;
   uint32_t g = blockIdx.x * kWaves + wv;
@@ -2118,9 +2140,9 @@ __global__ void __launch_bounds__(kBlock) k_local(Ws ws, int L) {
   }
 }
 
-// Groups of kWaveCap < n <= kMidCap keys: one wave each (a workgroup of one
-// wave, 16 keys per lane), which costs far less per key than a whole
-// workgroup on a group of barely more than kWaveCap keys.
+// Groups of wave_job_cap(PW) < n <= kMidCap keys: one wave each (a workgroup
+// of one wave, 16 keys per lane), which costs far less per key than a whole
+// workgroup on a group of barely more than a wave job.
 template <int PW>
 struct MidSmem {
   uint64_t k[kMidCap];
@@ -2142,7 +2164,7 @@ __global__ void __launch_bounds__(kWave) k_local_mid(Ws ws, int L) {
   for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
     const Leaf lf = ws.leavesm[S][g];
     const uint32_t n = lf.count;
-    if (n > (uint32_t)kMidCap) continue;   // (never: the list holds kWaveCap < n <= kMidCap)
+    if (n > (uint32_t)kMidCap) continue;   // (never: the list holds n <= kMidCap)
     moved += n;
     const bool ok = fast_sort<PW, 1, kMidCap / kWave>(sm.k, sm.pay, sm.cnt, nullptr, nullptr,
                                                       nullptr, ws.keys[lf.src], ws.pay[lf.src],
