@@ -152,7 +152,7 @@ size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
  * Statistics of the last call on `stream` (synchronises that stream).
  *   levels            number of recursion levels that held work
  *   device_error      0, or bits: 1 segment list, 2 work list, 4 leaf list,
- *                     8 look-back slots full, 16 look-back wait limit,
+ *                     8 scan rows full, 16 scan-row wait limit,
  *                     0x100 malformed segment offsets
  *   keys_per_level    keys distributed at each level
  *   segs_per_level    subproblems distributed at each level
@@ -231,7 +231,7 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
  * `stream` is bracketed by a pair of hipEvents recorded on that same stream;
  * _end synchronises the stream and sums the elapsed times per kernel kind:
  * index 0 moments, 1 finalize (statistics of the map), 2 histogram (with
- * look-back and classification), 3 stable scatter, 4 local sort (bucket
+ * cross-chunk scan and classification), 3 stable scatter, 4 local sort (bucket
  * pass), 5 local sort fallback (merge / radix).  launches[i] counts the
  * launches, including those of levels that found no work.
  */
@@ -242,6 +242,16 @@ typedef struct zsort_kernel_times {
 
 int zsort_profile_begin(void* stream);
 int zsort_profile_end(void* stream, zsort_kernel_times* out /* host */);
+
+/*
+ * As zsort_profile_begin, but only the kernel kinds whose bit is set in
+ * stage_mask (bit i = index i above) are bracketed by events; the others run
+ * as without profiling, and their entries of zsort_kernel_times stay zero.
+ * Recording an event between kernels costs a few microseconds, so timing one
+ * kind disturbs the rest of the call less.  ZSORT_EINVAL for an empty mask
+ * or bits above 5.
+ */
+int zsort_profile_begin_stages(void* stream, uint32_t stage_mask);
 
 /*
  * Learned partition map for the first distribution pass (an extension: the

@@ -23,7 +23,8 @@ EXPORTED = [
     "zsort_default_config", "zsort_stable", "zsort_stable_p64", "zsort_stable_ex",
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
-    "zsort_strerror", "zsort_profile_begin", "zsort_profile_end", "zsort_autotune",
+    "zsort_strerror", "zsort_profile_begin", "zsort_profile_begin_stages", "zsort_profile_end",
+    "zsort_autotune",
     "zsort_default_learned_config", "zsort_stable_learned", "zsort_learned_sample",
     "zsort_mlp_forward", "zsort_mlp_thresholds", "zsort_mlp_init", "zsort_mlp_grad",
     "zsort_mlp_train",
@@ -123,6 +124,7 @@ def lib():
                                           P, P]
         L.zsort_autotune.argtypes = [P, P, I, Z, P, ctypes.c_int32, ctypes.c_char_p, P, P]
         L.zsort_profile_begin.argtypes = [P]
+        L.zsort_profile_begin_stages.argtypes = [P, ctypes.c_uint32]
         L.zsort_profile_end.argtypes = [P, P]
         U64 = ctypes.c_uint64
         L.zsort_default_learned_config.argtypes = [P]
@@ -286,8 +288,15 @@ def zsort_autotune(keys, payload=None, seg_offsets=None, cache_path=None, stream
     return {f: getattr(best, f) for f in ("k", "cutoff", "max_zlevels", "chunk", "tile")}
 
 
-def zsort_profile_begin(stream=None):
-    _check("zsort_profile_begin", lib().zsort_profile_begin(_stream(stream)))
+def zsort_profile_begin(stream=None, stages=None):
+    """Times every kernel kind, or only those named in `stages` (see STAGES)."""
+    if stages is None:
+        _check("zsort_profile_begin", lib().zsort_profile_begin(_stream(stream)))
+        return
+    mask = 0
+    for name in stages:
+        mask |= 1 << STAGES.index(name)
+    _check("zsort_profile_begin_stages", lib().zsort_profile_begin_stages(_stream(stream), mask))
 
 
 def zsort_profile_end(stream=None) -> dict:

@@ -77,7 +77,7 @@ struct Layout {
   size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
       off_leavesm[2],
       off_hard[2],
-      off_status, off_part,
+      off_status, off_arrive[2], off_part,
       off_bstart, off_subpre, off_tiles[2], off_trace, off_thist, total;
   size_t status_bytes;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
@@ -91,7 +91,10 @@ Layout plan(const Shape& s) {
   const uint64_t seg_cap = n / ((uint64_t)s.cutoff + 1) + 1;
   const uint64_t nchunks = (n + ch - 1) / ch;
   const uint64_t work_cap = nchunks + seg_cap;
-  const uint64_t status_cap = 2 * nchunks + 2;
+  // scan rows of one level: a segment of nch > 1 chunks holds more than
+  // (nch - 1) * chunk keys, so nch < 2 * count / chunk, and it takes at most
+  // 1.5 * nch rows (items + units): < 3 * count / chunk over the level
+  const uint64_t status_cap = 3 * nchunks + 2;
   // leaf jobs of one level: runs (<= children + segments), windows of kWindow
   // keys, leaves above kWindow (each may also end a group), copy pieces
   const uint64_t leaf_cap = 4 * seg_cap + 4 * (n / zs::kWindow) + n / zs::kCopyChunk +
@@ -117,10 +120,12 @@ Layout plan(const Shape& s) {
     L.off_leavesm[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_hard[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
-  // look-back words: [slot][k]; a learned first pass has one root of
-  // nchunks slots with kfirst clusters each
-  L.status_bytes = std::max<size_t>(status_cap * (size_t)s.k, (nchunks + 1) * (size_t)s.kfirst) * 8;
+  // scan rows [row][k]; a learned first pass has one root of nchunks work
+  // items with kfirst clusters each
+  L.status_bytes = std::max<size_t>(status_cap * (size_t)s.k,
+                                    ((size_t)zs::status_rows((uint32_t)nchunks) + 1) * (size_t)s.kfirst) * 8;
   L.off_status = take(L.status_bytes);
+  for (int i = 0; i < 2; ++i) L.off_arrive[i] = take(status_cap * 4);
   L.off_part = take(work_cap * 10 * 8);
   L.off_bstart = take(std::max<size_t>(seg_cap * (size_t)s.k, (size_t)s.kfirst) * 4);
   // 8192-key tiles: one row of k 16-bit prefix counts per 8192 keys
@@ -165,6 +170,7 @@ struct Workspace {
   bool has_last = false;
   // per-kernel event timing (zsort_profile_begin / _end)
   bool prof = false;
+  uint32_t prof_mask = 0;  // kernel kinds that are timed (bit = stage)
   // pacing of level launches: per level, a host copy of the next level's
   // segment count and an event recorded after the level's kernels
   uint32_t* h_nseg = nullptr;  // pinned, kMaxLevels + 1 words
@@ -187,8 +193,10 @@ void drop_graphs(Workspace* w) {
 
 hipError_t next_event(Workspace* w, hipEvent_t* ev) {
   if (w->ev_used == w->ev_pool.size()) {
+    // timing only: no system-scope fence (cache write-back and invalidate)
+    // when the event is recorded, which would slow the kernels around it
     hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
+    hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     if (r != hipSuccess) return r;
     w->ev_pool.push_back(e);
   }
@@ -198,7 +206,7 @@ hipError_t next_event(Workspace* w, hipEvent_t* ev) {
 
 // launches one stage, bracketed by events when the stream is being profiled
 hipError_t stage(Workspace* w, const Ws& ws, int L, int st_id, int grid, hipStream_t st) {
-  if (!w->prof) return zs::launch_stage(ws, L, st_id, grid, st);
+  if (!w->prof || !((w->prof_mask >> st_id) & 1u)) return zs::launch_stage(ws, L, st_id, grid, st);
   hipEvent_t a, b;
   hipError_t e = next_event(w, &a);
   if (e == hipSuccess) e = next_event(w, &b);
@@ -282,7 +290,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
       e = hipMemsetAsync(w->base, 0, sizeof(zs::Ctl), st);
       if (e != hipSuccess) return hip_fail(e);
     }
-    // fresh look-back region: no stale word may carry a live tag
+    // fresh scan rows: no stale word may carry a live tag
     e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
     if (e != hipSuccess) return hip_fail(e);
     w->device = dev;
@@ -291,6 +299,7 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
     w->laid_out = true;
     w->calls = 0;
   } else if (w->calls && (w->calls % 65536u) == 0) {
+    // tags repeat after 2^16 calls: clear the rows before they could
     if (capturing(st)) return ZSORT_ECAPTURE;
     e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
     if (e != hipSuccess) return hip_fail(e);
@@ -316,6 +325,7 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
     ws.hard[i] = (zs::Leaf*)(w->base + L.off_hard[i]);
   }
   ws.status = (uint64_t*)(w->base + L.off_status);
+  for (int i = 0; i < 2; ++i) ws.arrive[i] = (uint32_t*)(w->base + L.off_arrive[i]);
   ws.part = (uint64_t*)(w->base + L.off_part);
   ws.bstart = (uint32_t*)(w->base + L.off_bstart);
   ws.subpre = (uint16_t*)(w->base + L.off_subpre);
@@ -951,10 +961,16 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
 }
 
 int zsort_profile_begin(void* stream) {
+  return zsort_profile_begin_stages(stream, (1u << zs::NSTAGES) - 1u);
+}
+
+int zsort_profile_begin_stages(void* stream, uint32_t stage_mask) {
+  if (stage_mask == 0 || (stage_mask >> zs::NSTAGES) != 0) return ZSORT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   Workspace*& w = g_ws[(hipStream_t)stream];
   if (!w) w = new Workspace();
   w->prof = true;
+  w->prof_mask = stage_mask;
   w->ev_used = 0;
   w->ev_stage.clear();
   return ZSORT_OK;

@@ -7,9 +7,10 @@
 // each level runs four kernels over all of its segments at once:
 //   moments  -- exact integer min/max/sum/sum of squares, then finalize
 //               (mean, std, Zmin, scale -> the map's A and B)
-//   hist     -- per-chunk cluster histogram, decoupled look-back prefix
-//               across the chunks of a segment, and (last chunk) the
-//               exclusive scan + classification of the clusters
+//   hist     -- per-chunk cluster histogram, the prefix across the chunks
+//               of a segment (reduce, then scan, by the last workgroups to
+//               arrive), and the exclusive scan + classification of the
+//               clusters
 //   scatter  -- stable scatter of key+payload to the other buffer
 //   local    -- in-LDS stable sort of the small clusters of this level
 // The recursion never returns to the host: each kernel reads its work count
@@ -35,6 +36,23 @@ constexpr int kMidCap = 1024;          // largest block job that one wave of k_l
 constexpr int kWindow = 256;           // leaf-group window; larger leaves sort alone
 constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
 
+// Cross-chunk scan of a segment of nch > 1 work items (reduce, then scan):
+// the items are grouped into scan units of scan_unit(nch) consecutive items,
+// a power of two near sqrt(nch), so that neither the pass over one unit's
+// rows nor the pass over the unit totals is long.  A segment owns
+// status_rows(nch) rows of k counts: one per item, then one per unit.
+__host__ __device__ constexpr uint32_t scan_unit(uint32_t nch) {
+  uint32_t u = 8;
+  while (u < 256 && u * u < nch) u <<= 1;
+  return u;
+}
+__host__ __device__ constexpr uint32_t scan_units(uint32_t nch) {
+  return (nch + scan_unit(nch) - 1) / scan_unit(nch);
+}
+__host__ __device__ constexpr uint32_t status_rows(uint32_t nch) {
+  return nch > 1 ? nch + scan_units(nch) : 0u;
+}
+
 // the kernels of a level, in launch order
 enum : int { STAGE_MOMENTS = 0, STAGE_FINALIZE = 1, STAGE_HIST = 2, STAGE_SCATTER = 3,
              STAGE_LOCAL = 4, STAGE_LOCAL_HARD = 5, NSTAGES = 6 };
@@ -56,7 +74,7 @@ struct __attribute__((aligned(16))) Seg {
   uint32_t flags;
   uint32_t first_work;   // first chunk's index in the level's work list
   uint32_t nchunks;
-  uint32_t status_base;  // first look-back slot (segments of > 1 chunk)
+  uint32_t status_base;  // first scan row (segments of > 1 chunk)
   uint32_t lm_base;      // learned map: first threshold of this segment's window
   int32_t parent;        // index of the parent in the previous level's list
   uint32_t lm_cnt;       // learned map: thresholds in the window (stride in `shift`)
@@ -86,9 +104,9 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nleafm[2];            // one-wave jobs of wave_job_cap(pw) < n <= kMidCap keys
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
+  uint32_t tick[kMaxLevels];     // work-item tickets of the hist pass
   uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list
-  uint32_t tick[kMaxLevels];     // in-order chunk tickets of the hist pass
-  uint32_t epoch;                // changes every call; tags look-back words
+  uint32_t epoch;                // changes every call; tags the scan rows
   uint32_t error;                // nonzero: a capacity or wait limit was hit
   uint32_t ntrace;
   uint32_t ntrace_hist;
@@ -187,9 +205,13 @@ struct Ws {
   Leaf* leavesw[2];      // wave jobs
   Leaf* leavesm[2];      // mid-size jobs (one wave, up to kMidCap keys)
   Leaf* hard[2];         // jobs for the fallback local sort
-  uint64_t* status;      // look-back words, [slot][k]
+  uint64_t* status;      // scan rows [row][k], tagged words: a work item's counts,
+                         // turned into its inclusive prefix within its unit; then
+                         // each unit's exclusive prefix over the segment's units
   uint64_t* part;        // per work item: 8 digit sums, min, max (moments pass)
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
+  uint32_t* arrive[2];   // per level slot: arrivals per scan unit, then per segment,
+                         // indexed like the scan rows (zeroed when the segment is made)
   uint16_t* subpre;      // 8192-key tiles: each cluster's count in a work item before
                          // the tile that starts at key position p, row p >> 13, [row][k]
   uint64_t* tiles[2];    // 8192-key tiles: (segment << 32) | (chunk << 3) | tile, the scatter's items

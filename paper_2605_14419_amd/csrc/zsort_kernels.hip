@@ -384,25 +384,53 @@ __device__ __forceinline__ void for_each_key(const uint64_t* __restrict__ x, uin
   }
 }
 
-// ---------------------------------------------------------------------------
-// look-back status words: tag(22) | flag(2) | value(40)
-// ---------------------------------------------------------------------------
-constexpr uint64_t kValMask = (1ull << 40) - 1;
-constexpr uint32_t FL_AGG = 1u, FL_INC = 2u;
-constexpr uint32_t kSpinLimit = 1u << 20;
-
 // a capacity or wait limit was hit earlier in this call: later kernels stop
 __device__ __forceinline__ bool call_failed(const Ctl* c) {
   return __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
 }
 
+// ---------------------------------------------------------------------------
+// scan rows shared between the workgroups of a level: words tag(22) |
+// value(40), stored and loaded at device scope.  No fence orders a row
+// before the arrival count that announces it (a device-scope fence writes
+// back and invalidates a whole L2); instead a reader that finds an older tag
+// waits for the word itself, which at most takes the store's flight time.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kValMask = (1ull << 40) - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
 __device__ __forceinline__ uint32_t level_tag(uint32_t epoch, int L) {
   return (epoch * 64u + (uint32_t)L) & 0x3FFFFFu;
 }
-__device__ __forceinline__ void st_publish(uint64_t* p, uint32_t tag, uint32_t flag, uint64_t v) {
-  uint64_t w = ((uint64_t)tag << 42) | ((uint64_t)flag << 40) | (v & kValMask);
-  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void row_put(uint64_t* p, uint32_t tag, uint64_t v) {
+  __hip_atomic_store(p, ((uint64_t)tag << 42) | (v & kValMask), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t row_peek(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the value of a word already loaded as w, once it carries `tag`
+__device__ __forceinline__ uint32_t row_value(const uint64_t* p, uint64_t w, uint32_t tag, Ctl* c) {
+  uint32_t spins = 0;
+  while ((uint32_t)(w >> 42) != tag) {
+    if (++spins > kSpinLimit || ((spins & 255u) == 0u && call_failed(c))) {
+      atomicOr(&c->error, ERR_SPIN);
+      return 0u;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    w = row_peek(p);
+  }
+  return (uint32_t)(w & kValMask);
+}
+
+// arrival counters of a new segment of nch chunks: one per scan unit, one for
+// the segment (the level's hist pass counts on them starting at zero)
+__device__ __forceinline__ void clear_arrivals(uint32_t* arr, uint32_t nch) {
+  if (nch > 1)
+    for (uint32_t i = 0, e = scan_units(nch); i <= e; ++i) arr[i] = 0u;
+}
+
+
 
 // ---------------------------------------------------------------------------
 // reset + level-0 set-up
@@ -495,6 +523,14 @@ __device__ void init_root_tiles(Ws& ws, uint64_t n) {
     ws.tiles[0][u] = tile_entry(0u, u, nsub);
 }
 
+// arrival counters of the single root segment (rows from 0)
+__device__ void init_root_arrivals(Ws& ws, uint32_t nch) {
+  if (nch <= 1) return;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= scan_units(nch);
+       i += gridDim.x * blockDim.x)
+    ws.arrive[0][i] = 0u;
+}
+
 // one array [0, n): root segment (n > cutoff) or a single leaf
 __global__ void k_init_single(Ws ws, uint64_t n) {
   Ctl* c = ws.ctl;
@@ -511,10 +547,11 @@ __global__ void k_init_single(Ws ws, uint64_t n) {
     make_root_seg(ws, 0, 0, n, 0, nch, 0);
     c->nseg[0] = 1;
     c->nwork[0] = nch;
-    c->nstatus[0] = nch > 1 ? nch : 0;
+    c->nstatus[0] = status_rows(nch);
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
     ws.work[0][i] = (uint64_t)i;  // segment 0, chunk i
+  init_root_arrivals(ws, nch);
   init_root_tiles(ws, n);
 }
 
@@ -546,10 +583,11 @@ __global__ void k_init_learned(Ws ws, uint64_t n) {
     s.shift = sub ? (int32_t)sub : 1;
     c->nseg[0] = 1;
     c->nwork[0] = nch;
-    c->nstatus[0] = nch > 1 ? nch : 0;
+    c->nstatus[0] = status_rows(nch);
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nch; i += gridDim.x * blockDim.x)
     ws.work[0][i] = (uint64_t)i;
+  init_root_arrivals(ws, nch);
   init_root_tiles(ws, n);
 }
 
@@ -579,12 +617,13 @@ __global__ void k_init_segments(Ws ws, const int64_t* off, int32_t nseg) {
     const uint32_t nch = (uint32_t)((len + ch - 1) / ch);
     uint32_t si = atomicAdd(&c->nseg[0], 1u);
     uint32_t wi = atomicAdd(&c->nwork[0], nch);
-    uint32_t sb = nch > 1 ? atomicAdd(&c->nstatus[0], nch) : 0u;
-    if (si >= ws.seg_cap || wi + nch > ws.work_cap || sb + (nch > 1 ? nch : 0) > ws.status_cap) {
+    uint32_t sb = nch > 1 ? atomicAdd(&c->nstatus[0], status_rows(nch)) : 0u;
+    if (si >= ws.seg_cap || wi + nch > ws.work_cap || sb + status_rows(nch) > ws.status_cap) {
       atomicOr(&c->error, ERR_SEGCAP);
       continue;
     }
     make_root_seg(ws, si, a, len, wi, nch, sb);
+    clear_arrivals(ws.arrive[0] + sb, nch);
     for (uint32_t j = 0; j < nch; ++j) ws.work[0][wi + j] = ((uint64_t)si << 32) | j;
     const uint32_t nsub = tiles_per_item(ws);
     if (nsub > 1) {
@@ -842,8 +881,9 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
 }
 
 // ---------------------------------------------------------------------------
-// hist: per-chunk LDS histogram, decoupled look-back over the chunks of a
-// segment, and in the last chunk the exclusive scan + classification
+// hist: per-chunk LDS histogram, the scan over the chunks of a segment
+// (reduce, then scan: the last arrivals do it), and the exclusive scan +
+// classification of the segment's clusters
 // ---------------------------------------------------------------------------
 template <int KMAX>
 struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned thresholds)
@@ -857,6 +897,7 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t t2[KMAX];
   uint32_t sh[kWaves + 2];
   uint32_t w;
+  uint32_t last;          // this workgroup arrived last at a scan unit / segment
   uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid;
   // statistics of this workgroup's segments, added to the control block at
   // the end of the kernel
@@ -880,14 +921,14 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
   for (int b = t; b < k; b += kBlock) gb[b] = sm.bst[b];
 
-  // children: index, chunk offset, look-back slot offset
+  // children: index, chunk offset, scan row offset
   for (int b = t; b < k; b += kBlock) {
     const uint32_t n = sm.h[b];
     const bool child = n > cutoff;
     const uint32_t nch = child ? (uint32_t)((n + ch - 1) / ch) : 0u;
     sm.t0[b] = child ? 1u : 0u;
     sm.t1[b] = nch;
-    sm.t2[b] = nch > 1 ? nch : 0u;
+    sm.t2[b] = status_rows(nch);
     if constexpr (KMAX <= 1024) sm.hq[b] = child ? (n + 8191u) >> 13 : 0u;  // 8192-key tiles
   }
   __syncthreads();
@@ -942,6 +983,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       cs.nchunks = (uint32_t)((n + ch - 1) / ch);
       cs.first_work = sm.base_work + sm.t1[b];
       cs.status_base = sm.base_status + sm.t2[b];
+      clear_arrivals(ws.arrive[N] + cs.status_base, cs.nchunks);
       cs.parent = (int32_t)si;
       seg_clear_acc(cs);
       if (parent_l && ws.lm.sub) {
@@ -1132,7 +1174,6 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   const int k = ws.p.k;
   const uint64_t ch = (uint64_t)ws.p.chunk;
   const uint64_t* __restrict__ x = ws.keys[S];
-  const uint32_t tag = level_tag(c->epoch, L);
   const int t = threadIdx.x;
   // tiles of the scatter per work item, each with its own starts (8192-key
   // tiles only, at most 8)
@@ -1143,6 +1184,8 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     sm.st_groups = 0;
   }
 
+  // items by ticket (the last arrivals at a scan unit or segment do more
+  // work, so a fixed share per workgroup would be uneven)
   while (true) {
     if (t == 0) sm.w = atomicAdd(&c->tick[L], 1u);
     __syncthreads();
@@ -1212,41 +1255,79 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
       }
       __syncthreads();
     }
+    // Across the chunks of a segment: reduce, then scan -- nothing waits.
+    // The chunk's counts go to its row; the last chunk of a scan unit to
+    // arrive turns the unit's rows into running sums within the unit and
+    // keeps the unit's totals in the unit's row; the last unit of the segment
+    // to arrive turns the unit totals into exclusive prefixes and has the
+    // segment's totals, which it classifies.  A chunk's exclusive start is
+    // then its unit's prefix plus the row before it in its unit.
     const uint32_t nch = sg.nchunks;
+    bool seg_done = nch == 1;
     if (nch > 1) {
-      uint64_t* st0 = ws.status + (uint64_t)sg.status_base * (uint64_t)k;
-      uint64_t* st = st0 + (uint64_t)ci * (uint64_t)k;
-      if (ci == 0) {
-        for (int b = t; b < k; b += kBlock) st_publish(st + b, tag, FL_INC, sm.h[b]);
-      } else {
-        const bool lastc = ci == nch - 1;
-        if (!lastc)
-          for (int b = t; b < k; b += kBlock) st_publish(st + b, tag, FL_AGG, sm.h[b]);
+      const uint32_t tag = level_tag(c->epoch, L);
+      const uint32_t u = scan_unit(nch), nun = scan_units(nch);
+      const uint32_t un = ci / u, r0 = un * u, r1 = min(r0 + u, nch);
+      uint64_t* rows = ws.status + (uint64_t)sg.status_base * (uint64_t)k;
+      uint32_t* arr = ws.arrive[S] + sg.status_base;
+      for (int b = t; b < k; b += kBlock) row_put(rows + (uint64_t)ci * k + b, tag, sm.h[b]);
+      __syncthreads();
+      if (t == 0) sm.last = atomicAdd(&arr[un], 1u) == r1 - r0 - 1u ? 1u : 0u;
+      __syncthreads();
+      if (sm.last) {
+        constexpr uint32_t B = 16;  // rows in flight per thread
         for (int b = t; b < k; b += kBlock) {
-          uint64_t excl = 0;
-          int j = (int)ci - 1;
-          uint32_t spins = 0;
-          while (true) {
-            const uint64_t wv = __hip_atomic_load(st0 + (uint64_t)j * (uint64_t)k + b,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t wt = (uint32_t)(wv >> 42), wf = (uint32_t)(wv >> 40) & 3u;
-            if (wt != tag || wf == 0) {
-              if (++spins > kSpinLimit) { atomicOr(&c->error, ERR_SPIN); break; }
-              __builtin_amdgcn_s_sleep(1);
-              continue;
+          uint32_t run = 0;
+          for (uint32_t r = r0; r < r1; r += B) {
+            uint64_t v[B];
+#pragma unroll
+            for (uint32_t j = 0; j < B; ++j)
+              v[j] = r + j < r1 ? row_peek(rows + (uint64_t)(r + j) * k + b) : 0ull;
+#pragma unroll
+            for (uint32_t j = 0; j < B; ++j) {
+              if (r + j < r1) {
+                uint64_t* p = rows + (uint64_t)(r + j) * k + b;
+                run += row_value(p, v[j], tag, c);
+                row_put(p, tag, run);
+              }
             }
-            excl += wv & kValMask;
-            if (wf == FL_INC) break;
-            --j;
           }
-          const uint64_t inc = excl + sm.h[b];
-          if (!lastc) st_publish(st + b, tag, FL_INC, inc);
-          else sm.h[b] = (uint32_t)inc;  // totals of the segment
+          if (nun == 1) sm.h[b] = run;
+          else row_put(rows + (uint64_t)(nch + un) * k + b, tag, run);
+        }
+        if (nun == 1) {
+          seg_done = true;
+        } else {
+          __syncthreads();
+          if (t == 0) sm.last = atomicAdd(&arr[nun], 1u) == nun - 1u ? 1u : 0u;
+          __syncthreads();
+          if (sm.last) {
+            for (int b = t; b < k; b += kBlock) {
+              uint32_t run = 0;
+              for (uint32_t q = 0; q < nun; q += B) {
+                uint64_t v[B];
+#pragma unroll
+                for (uint32_t j = 0; j < B; ++j)
+                  v[j] = q + j < nun ? row_peek(rows + (uint64_t)(nch + q + j) * k + b) : 0ull;
+#pragma unroll
+                for (uint32_t j = 0; j < B; ++j) {
+                  if (q + j < nun) {
+                    uint64_t* p = rows + (uint64_t)(nch + q + j) * k + b;
+                    const uint32_t x = row_value(p, v[j], tag, c);
+                    row_put(p, tag, run);
+                    run += x;
+                  }
+                }
+              }
+              sm.h[b] = run;  // totals of the segment
+            }
+            seg_done = true;
+          }
         }
       }
     }
     __syncthreads();
-    if (ci == nch - 1) classify<KMAX>(ws, sm, sg, si, L);
+    if (seg_done) classify<KMAX>(ws, sm, sg, si, L);
     __syncthreads();
   }
   if (t == 0) {
@@ -1348,13 +1429,25 @@ __global__ void __launch_bounds__(SB, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, in
     const uint64_t end = min(beg + span, sg.start + sg.count);
     if (beg >= end) continue;
     const uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
-    const uint64_t* stp = (ci > 0) ? ws.status + (uint64_t)(sg.status_base + ci - 1) * (uint64_t)k : nullptr;
+    // start of each cluster: the segment's exclusive start, the prefix of
+    // the chunk's scan unit, the running count within the unit before the
+    // chunk, and (8192-key tiles) the count before the tile within the chunk
+    const uint32_t nch = sg.nchunks;
+    const uint32_t su = nch > 1 ? scan_unit(nch) : 1u;
+    const uint64_t* rows = ws.status + (uint64_t)sg.status_base * (uint64_t)k;
+    const uint64_t* rp = (ci % su) ? rows + (uint64_t)(ci - 1) * (uint64_t)k : nullptr;
+    const uint64_t* up = (ci / su) ? rows + (uint64_t)(nch + ci / su) * (uint64_t)k : nullptr;
     const uint16_t* spp = sub > 0 ? ws.subpre + (beg >> 13) * (uint64_t)k : nullptr;
+    // (all four loads are issued before any is used: one memory latency)
+    const uint64_t seg0 = sg.start;
     for (int b = t; b < k; b += SB) {
-      uint64_t base = sg.start + gb[b];
-      if (stp) base += stp[b] & kValMask;
-      if (spp) base += spp[b];
-      sm.gbase[b] = (uint32_t)base;
+      uint64_t vr = 0, vu = 0;
+      uint32_t vs = 0;
+      if (rp) vr = rp[b];
+      if (up) vu = up[b];
+      if (spp) vs = spp[b];
+      const uint32_t g = gb[b];
+      sm.gbase[b] = (uint32_t)(seg0 + g + (vr & kValMask) + (vu & kValMask) + vs);
     }
     // segment bounds in registers (a reference into global memory would be
     // re-read after every store the compiler cannot prove apart from it)

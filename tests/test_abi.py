@@ -73,6 +73,9 @@ def test_entry_points_reject_bad_arguments_without_touching_the_gpu():
     assert L.zsort_stable_ex(None, None, 0, 10, None, None) == zs.ZSORT_EINVAL
     assert L.zsort_stable_ex(ctypes.c_void_p(16), None, 4, 10, None, None) == zs.ZSORT_EINVAL
     assert L.zsort_stable_ex(ctypes.c_void_p(16), None, 0, 2**31, None, None) == zs.ZSORT_EINVAL
+    # profiling of no kernel kind, or of kinds that do not exist
+    assert L.zsort_profile_begin_stages(None, 0) == zs.ZSORT_EINVAL
+    assert L.zsort_profile_begin_stages(None, 1 << len(zs.STAGES)) == zs.ZSORT_EINVAL
     # n <= 1 is a no-op
     assert L.zsort_stable_ex(None, None, 0, 1, None, None) == zs.ZSORT_OK
     bad = zs.zsort_default_config(k=5000)

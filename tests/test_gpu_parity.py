@@ -198,6 +198,25 @@ def test_repeat_calls_identical():
         assert np.array_equal(k, outs[0][0]) and np.array_equal(p, outs[0][1])
 
 
+def test_profiling_one_kernel_kind_leaves_the_sort_unchanged():
+    x, idx = synth.make("lognormal", 300_000)
+    ok, oi, _ = oracle.sort(x, idx, **{kk: CFG[kk] for kk in ("k", "cutoff", "max_zlevels")})
+    say("case profile stages")
+    tk, tp = to_dev(x, idx)
+    zs.zsort_profile_begin(stages=["scatter"])
+    zs.zsort_stable_ex(tk, tp, CFG)
+    kt = zs.zsort_profile_end()
+    k, p = from_dev(tk, tp, idx.dtype)
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
+    assert kt["scatter"][1] >= 1 and kt["scatter"][0] > 0
+    assert all(kt[s] == (0.0, 0) for s in zs.STAGES if s != "scatter")
+    tk, tp = to_dev(x, idx)
+    zs.zsort_profile_begin()
+    zs.zsort_stable_ex(tk, tp, CFG)
+    kt = zs.zsort_profile_end()
+    assert all(kt[s][1] >= 1 for s in ("moments", "finalize", "hist", "scatter", "local"))
+
+
 @pytest.mark.parametrize("name", ["uniform", "normal", "dup_heavy", "partial", "descending"])
 def test_ten_million_vs_oracle(name):
     """the five 10^7 arrays of the plain-path workload, full size"""
