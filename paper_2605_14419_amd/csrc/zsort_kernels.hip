@@ -170,6 +170,70 @@ __device__ uint32_t block_scan_lds(uint32_t* a, int N, uint32_t* sh) {
 }
 
 // in-place exclusive max over a[0, N) in LDS (identity -1)
+// NA exclusive scans of N-element LDS arrays in one pass (two barriers for
+// all of them); tot receives each array's total
+template <int NA>
+__device__ void block_scan_multi(uint32_t* const (&a)[NA], int N, uint32_t (*sh)[kWaves],
+                                 uint32_t (&tot)[NA]) {
+  const int ipt = (N + kBlock - 1) / kBlock;
+  const int b0 = threadIdx.x * ipt;
+  uint32_t s[NA], inc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    s[q] = 0;
+    for (int i = 0; i < ipt; ++i)
+      if (b0 + i < N) s[q] += a[q][b0 + i];
+    inc[q] = wave_incl_sum(s[q]);
+    if (lane() == kWave - 1) sh[q][wave()] = inc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    uint32_t base = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t v = sh[q][w];
+      base += (w < (int)wave()) ? v : 0u;
+      t += v;
+    }
+    tot[q] = t;
+    base += inc[q] - s[q];
+    for (int i = 0; i < ipt; ++i) {
+      if (b0 + i < N) {
+        const uint32_t x = a[q][b0 + i];
+        a[q][b0 + i] = base;
+        base += x;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// three exclusive sums of one value per thread at once
+__device__ __forceinline__ void block_excl_sum3(const uint32_t (&v)[3], uint32_t (*sh)[kWaves],
+                                                uint32_t (&ex)[3], uint32_t (&tot)[3]) {
+  uint32_t inc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    inc[q] = wave_incl_sum(v[q]);
+    if (lane() == kWave - 1) sh[q][wave()] = inc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    uint32_t base = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t x = sh[q][w];
+      base += (w < (int)wave()) ? x : 0u;
+      t += x;
+    }
+    ex[q] = base + inc[q] - v[q];
+    tot[q] = t;
+  }
+  __syncthreads();
+}
+
 __device__ void block_excl_max_lds(int* a, int N, int* sh) {
   const int ipt = (N + kBlock - 1) / kBlock;
   const int b0 = threadIdx.x * ipt;
@@ -803,6 +867,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
 // (exact, order-free integer sums), then one thread derives the statistics
 constexpr int kFinThreads = kBlock;  // workgroup of the finalize kernel
 constexpr uint32_t kFinBig = 256;   // segments with more chunks are summed by a whole workgroup
+constexpr uint32_t kFinLane = 4;    // segments with at most this many chunks: one lane each
 
 // sums of partials [q0, q1) with stride `step`, two chunks in flight per lane
 __device__ __forceinline__ void sum_partials(const uint64_t* part, uint32_t q0, uint32_t q1,
@@ -861,22 +926,42 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
     }
     __syncthreads();
   }
-  // the others: one wave each, whose lanes sum the chunk partials and whose
-  // lane 0 computes the statistics (waves of a workgroup work on different
-  // segments)
+  // middle sizes: one wave each, whose lanes sum the chunk partials and
+  // whose lane 0 computes the statistics (waves of a workgroup work on
+  // different segments)
   const uint32_t nwv = gridDim.x * NWV;
   for (uint32_t i = blockIdx.x * NWV + wv; i < ns; i += nwv) {
     Seg& sg = ws.segs[S][i];
-    if (sg.nchunks >= kFinBig) continue;
+    if (sg.nchunks >= kFinBig || sg.nchunks <= kFinLane) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
     sum_partials(ws.part + (uint64_t)sg.first_work * 10, ln, sg.nchunks, kWave, v);
     wave_reduce_moments(v);
     if (ln == 0) finalize(ws, sg, L, v, fs);
   }
+  // the many small segments of the deeper levels: one lane each, which sums
+  // its few partials itself (the statistics are serial work of one lane in
+  // any case, so 64 of them run side by side)
+  const uint32_t nln = nwv * kWave;
+  for (uint32_t i = (blockIdx.x * NWV + wv) * kWave + ln; i < ns; i += nln) {
+    Seg& sg = ws.segs[S][i];
+    if (sg.nchunks > kFinLane) continue;
+    uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
+    sum_partials(ws.part + (uint64_t)sg.first_work * 10, 0u, sg.nchunks, 1u, v);
+    finalize(ws, sg, L, v, fs);
+  }
+  // statistics of the wave's segments
+  uint64_t mk = fs.mkeys;
+  uint32_t id = fs.ident, rm = fs.rmap;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    mk += __shfl_xor(mk, d);
+    id += __shfl_xor(id, d);
+    rm += __shfl_xor(rm, d);
+  }
   if (ln == 0) {
-    if (fs.mkeys) atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)fs.mkeys);
-    if (fs.ident) atomicAdd(&c->n_ident, fs.ident);
-    if (fs.rmap) atomicAdd(&c->n_rmap, fs.rmap);
+    if (mk) atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)mk);
+    if (id) atomicAdd(&c->n_ident, id);
+    if (rm) atomicAdd(&c->n_rmap, rm);
   }
 }
 
@@ -896,6 +981,7 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t t1[KMAX];
   uint32_t t2[KMAX];
   uint32_t sh[kWaves + 2];
+  uint32_t shm[5][kWaves];  // wave totals of the multi-array scans
   uint32_t w;
   uint32_t last;          // this workgroup arrived last at a scan unit / segment
   uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid;
@@ -914,31 +1000,35 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   const int S = L & 1, N = S ^ 1;
   const int t = threadIdx.x;
 
-  // exclusive cluster starts
-  for (int b = t; b < k; b += kBlock) sm.bst[b] = sm.h[b];
-  __syncthreads();
-  block_scan_lds(sm.bst, k, sm.sh);
-  uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
-  for (int b = t; b < k; b += kBlock) gb[b] = sm.bst[b];
-
-  // children: index, chunk offset, scan row offset
+  // exclusive cluster starts, and per child: index, chunk offset, scan row
+  // offset, tile offset -- five scans in one pass
   for (int b = t; b < k; b += kBlock) {
     const uint32_t n = sm.h[b];
     const bool child = n > cutoff;
     const uint32_t nch = child ? (uint32_t)((n + ch - 1) / ch) : 0u;
+    sm.bst[b] = n;
     sm.t0[b] = child ? 1u : 0u;
     sm.t1[b] = nch;
     sm.t2[b] = status_rows(nch);
     if constexpr (KMAX <= 1024) sm.hq[b] = child ? (n + 8191u) >> 13 : 0u;  // 8192-key tiles
   }
   __syncthreads();
-  const uint32_t nchild = block_scan_lds(sm.t0, k, sm.sh);
-  const uint32_t nwork = block_scan_lds(sm.t1, k, sm.sh);
-  const uint32_t nstat = block_scan_lds(sm.t2, k, sm.sh);
   const uint32_t nsub = tiles_per_item(ws);
-  uint32_t ntiles = 0;
-  if constexpr (KMAX <= 1024)
-    if (nsub > 1) ntiles = block_scan_lds(sm.hq, k, sm.sh);
+  uint32_t nchild, nwork, nstat, ntiles = 0;
+  if constexpr (KMAX <= 1024) {
+    uint32_t* const arr[5] = {sm.bst, sm.t0, sm.t1, sm.t2, sm.hq};
+    uint32_t tot[5];
+    block_scan_multi<5>(arr, k, sm.shm, tot);
+    nchild = tot[1], nwork = tot[2], nstat = tot[3];
+    if (nsub > 1) ntiles = tot[4];
+  } else {
+    uint32_t* const arr[4] = {sm.bst, sm.t0, sm.t1, sm.t2};
+    uint32_t tot[4];
+    block_scan_multi<4>(arr, k, sm.shm, tot);
+    nchild = tot[1], nwork = tot[2], nstat = tot[3];
+  }
+  uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
+  for (int b = t; b < k; b += kBlock) gb[b] = sm.bst[b];
   if (t == 0) {
     sm.base_seg = nchild ? atomicAdd(&c->nseg[N], nchild) : 0u;
     sm.base_work = nwork ? atomicAdd(&c->nwork[N], nwork) : 0u;
@@ -1069,10 +1159,11 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
     else ++my_big;
   }
-  uint32_t nsmall, nmid, nbig;
-  const uint32_t off_small = block_excl_sum(my_small, sm.sh, &nsmall);
-  const uint32_t off_mid = block_excl_sum(my_mid, sm.sh, &nmid);
-  const uint32_t off_big = block_excl_sum(my_big, sm.sh, &nbig);
+  const uint32_t mine[3] = {my_small, my_mid, my_big};
+  uint32_t offs[3], tots[3];
+  block_excl_sum3(mine, sm.shm, offs, tots);
+  const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2];
+  const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2];
   if (t == 0) {
     sm.base_leaf = nsmall ? atomicAdd(&c->nleafw[S], nsmall) : 0u;
     sm.base_mid = nmid ? atomicAdd(&c->nleafm[S], nmid) : 0u;
