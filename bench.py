@@ -333,12 +333,13 @@ def roofline(kt, stats, pw, steps, traffic_file, cfg):
             "launches": launches}
 
 
-# kernel -> stage; the local stage launches two kernels (groups of up to 512
-# keys, then one wave per group of 513..1024): the first counts the launches
+# kernel -> stage; the local stage launches up to three kernels (wave and
+# block jobs, one wave per group up to 1024 keys, block jobs above 2048 keys):
+# the first counts the launches
 STAGE_OF_KERNEL = (("k_moments", "moments"), ("k_finalize", "finalize"), ("k_hist", "hist"),
                    ("k_scatter", "scatter"), ("k_local_hard", "local_hard"),
-                   ("k_local_mid", "local"), ("k_local", "local"))
-SECOND_KERNELS = ("k_local_mid",)
+                   ("k_local_mid", "local"), ("k_local_big", "local"), ("k_local", "local"))
+SECOND_KERNELS = ("k_local_mid", "k_local_big")
 
 
 def _stage_of(name):

@@ -56,7 +56,7 @@ enum {
  *                k = sqrt(n) held constant across levels (Section III, choice
  *                of k); here k is a constant "buckets per pass".  Default 1024.
  *   cutoff       clusters of at most this many keys are finished by the local
- *                (in-LDS) stable sort, 1..2048 (the paper's insertion-sort
+ *                (in-LDS) stable sort, 1..4096 (the paper's insertion-sort
  *                threshold is 96).  Default 2048.
  *   max_zlevels  depth at which the z-score map gives way to the exact range
  *                map, 0..16 (0 = range map everywhere).  Default 8.
@@ -99,7 +99,7 @@ int zsort_default_config(zsort_config* cfg);
 /*
  * Autotuner: times candidate configurations (k in {256, 512, 1024}; (tile,
  * chunk) in {(2048, 16384), (4096, 32768), (8192, 8192), (8192, 32768)};
- * cutoff in {1024, 2048}) on a scratch copy of keys/payload (device buffers,
+ * cutoff in {1024, 2048, 4096}) on a scratch copy of keys/payload (device buffers,
  * left unchanged; seg_offsets may be NULL for a single array) and remembers
  * the fastest for the shape class (n rounded up to a power of two, payload
  * width, single or segmented).

@@ -237,7 +237,7 @@ bool capturing(hipStream_t st) {
 
 int check_cfg(const zsort_config* c) {
   if (c->k < 16 || c->k > zs::kKMax) return ZSORT_EINVAL;
-  if (c->cutoff < 1 || c->cutoff > zs::kBlockCap) return ZSORT_EINVAL;
+  if (c->cutoff < 1 || c->cutoff > zs::kBigCap) return ZSORT_EINVAL;
   if (c->max_zlevels < 0 || c->max_zlevels > 16) return ZSORT_EINVAL;
   if (c->chunk < 2048 || c->chunk > (1 << 20) || c->chunk % 2048) return ZSORT_EINVAL;
   if (c->tile != 2048 && c->tile != 4096 && c->tile != 8192) return ZSORT_EINVAL;
@@ -915,10 +915,10 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
   // side by side in memory at the same time; larger ones cost the histogram
   // pass less
   const int tiles[4][2] = {{2048, 16384}, {4096, 32768}, {8192, 8192}, {8192, 32768}};
-  const int cuts[2] = {1024, 2048};
+  const int cuts[3] = {1024, 2048, 4096};
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
     for (int b = 0; b < 4 && e == hipSuccess; ++b)
-      for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+      for (int d = 0; d < 3 && e == hipSuccess; ++d) {
         zsort_config c;
         zsort_default_config(&c);
         c.k = ks[a];

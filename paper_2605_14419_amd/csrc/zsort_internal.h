@@ -26,7 +26,9 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxLevels = 40;
 constexpr int kKMax = 4096;            // largest clusters-per-pass supported
 constexpr int kLocalCap = 4096;        // largest group the fallback local sort takes
-constexpr int kBlockCap = 2048;        // largest group (= largest cutoff) of the fast local sort
+constexpr int kBlockCap = 2048;        // largest group of the fast local sort's main kernel
+constexpr int kBigCap = 4096;          // largest group (= largest cutoff) of the fast local sort:
+                                       // (kBlockCap, kBigCap] in a kernel of their own
 constexpr int kWaveCap = 512;          // largest group one wave of the fallback sort takes
 // largest group one wave of the fast local sort takes (wave jobs): 10 keys
 // per lane with payloads of up to 4 bytes, 8 with 8-byte payloads (the LDS of

@@ -2250,8 +2250,8 @@ __device__ __forceinline__ void local_body(Ws ws, int L) {
         }
       continue;
     }
-    if (n > (uint32_t)kBlockCap) {  // not produced by the grouping; left to the fallback
-      if (t == 0) push_hard(ws, S, lf);
+    if (n > (uint32_t)kBlockCap) {  // k_local_big's (above its cap: never made; the fallback)
+      if (n > (uint32_t)kBigCap && t == 0) push_hard(ws, S, lf);
       continue;
     }
     const bool ok = fast_sort<PW, kWaves, kBlockCap / kBlock>(
@@ -2358,6 +2358,40 @@ __global__ void __launch_bounds__(kWave) k_local_mid(Ws ws, int L) {
   if (ln == 0 && moved) atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)moved);
 }
 
+// Block jobs of kBlockCap < n <= kBigCap keys (cutoffs above kBlockCap): a
+// workgroup with 16 keys per thread, in a kernel of its own so that the main
+// kernel's LDS (and with it its occupancy) stays sized for kBlockCap.  The
+// main kernel counts these groups in its statistics.
+template <int PW>
+struct BigSmem {
+  uint64_t k[kBigCap];
+  typename PayT<PW>::T pay[PW ? kBigCap : 1];
+  uint32_t cnt[kBigCap / 2];
+  uint64_t rmin[kWaves], rmax[kWaves];
+  uint32_t sh[kWaves + 2];
+};
+
+template <int PW>
+__global__ void __launch_bounds__(kBlock) k_local_big(Ws ws, int L) {
+  __shared__ BigSmem<PW> sm;
+  Ctl* c = ws.ctl;
+  if (call_failed(c)) return;
+  const int S = L & 1;
+  const uint32_t nl = min(c->nleaf[S], ws.leaf_cap);
+  uint64_t* __restrict__ dst = ws.keys[0];
+  void* pdst = ws.pay[0];
+  const int t = threadIdx.x;
+  for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
+    const Leaf lf = ws.leaves[S][g];
+    const uint32_t n = lf.count;
+    if ((lf.flags & LF_COPY) || n <= (uint32_t)kBlockCap || n > (uint32_t)kBigCap) continue;
+    const bool ok = fast_sort<PW, kWaves, kBigCap / kBlock>(
+        sm.k, sm.pay, sm.cnt, sm.rmin, sm.rmax, sm.sh, ws.keys[lf.src], ws.pay[lf.src], dst, pdst,
+        lf.start, n, (uint32_t)t);
+    if (!ok && t == 0) push_hard(ws, S, lf);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -2373,21 +2407,28 @@ static const void* stage_fn(int stage) {
   }
 }
 
-// resident one-wave workgroups of k_local_mid on the whole device
+// resident workgroups of a kernel on the whole device (at most 16 per CU)
+static int resident_grid(const void* fn, int threads) {
+  int nb = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  return (nb < 16 ? nb : 16) * cus;
+}
+// one-wave workgroups of k_local_mid
 template <int PW>
 static int mid_grid() {
   static int g = 0;
-  if (g == 0) {
-    int nb = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_local_mid<PW>, kWave, 0) !=
-            hipSuccess || nb < 1)
-      nb = 1;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus < 1)
-      cus = 1;
-    g = (nb < 16 ? nb : 16) * cus;
-  }
+  if (g == 0) g = resident_grid((const void*)k_local_mid<PW>, kWave);
+  return g;
+}
+template <int PW>
+static int big_grid() {
+  static int g = 0;
+  if (g == 0) g = resident_grid((const void*)k_local_big<PW>, kBlock);
   return g;
 }
 
@@ -2415,6 +2456,8 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
     case STAGE_LOCAL:
       hipLaunchKernelGGL((k_local<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       hipLaunchKernelGGL((k_local_mid<PW>), dim3(mid_grid<PW>()), dim3(kWave), 0, st, ws, L);
+      if (ws.p.cutoff > kBlockCap)  // groups above kBlockCap exist only then
+        hipLaunchKernelGGL((k_local_big<PW>), dim3(big_grid<PW>()), dim3(kBlock), 0, st, ws, L);
       break;
     default:
       hipLaunchKernelGGL((k_local_hard<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);

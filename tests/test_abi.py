@@ -63,7 +63,7 @@ def test_host_only_entry_points():
     assert 12 * 10**8 <= b <= 20 * 10**8
     assert zs.zsort_workspace_bytes(10**8, 3, 0) == 0        # bad payload width
     assert zs.zsort_workspace_bytes(100, 4, 0, dict(k=8)) == 0  # k below 16
-    assert zs.zsort_workspace_bytes(100, 4, 0, dict(cutoff=4096)) == 0
+    assert zs.zsort_workspace_bytes(100, 4, 0, dict(cutoff=8192)) == 0
 
 
 def test_entry_points_reject_bad_arguments_without_touching_the_gpu():

@@ -198,6 +198,23 @@ def test_repeat_calls_identical():
         assert np.array_equal(k, outs[0][0]) and np.array_equal(p, outs[0][1])
 
 
+@pytest.mark.parametrize("name,pw", [("lognormal", 8), ("normal", 4), ("dup_heavy", 8),
+                                     ("uniform", 0), ("zipf", 4)])
+def test_cutoff_4096_vs_oracle(name, pw):
+    # leaves of 2049..4096 keys: the block jobs of their own kernel, and (wide
+    # ranges, duplicates) its fallback to the merge / radix sort
+    n = 3_000_000
+    x, pay = synth.make(name, n, payload_bytes=pw)
+    cfg = dict(k=256, cutoff=4096, max_zlevels=8, chunk=16384)
+    say("case cutoff 4096", name, pw)
+    k, p, st = gpu_sort(x, pay, cfg)
+    assert st["device_error"] == 0
+    ok, op, _ = oracle.sort(x, pay, k=256, cutoff=4096, max_zlevels=8)
+    assert np.array_equal(k, ok)
+    if pw:
+        assert np.array_equal(p, op)
+
+
 def test_profiling_one_kernel_kind_leaves_the_sort_unchanged():
     x, idx = synth.make("lognormal", 300_000)
     ok, oi, _ = oracle.sort(x, idx, **{kk: CFG[kk] for kk in ("k", "cutoff", "max_zlevels")})
