@@ -1094,26 +1094,22 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     for (int b = t; b < k; b += kBlock)
       if (sm.h[b] > cutoff) sm.t2[sm.t0[b]] = (uint32_t)b;  // t2 reused: child -> bucket
     __syncthreads();
-    for (uint32_t j = t; j < nwork; j += kBlock) {
-      // find the child whose chunk range holds j (binary search on t1 over children)
-      uint32_t lo = 0, hi = nchild;  // invariant: t1[bucket(lo)] <= j
-      while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (sm.t1[sm.t2[mid]] <= j) lo = mid; else hi = mid;
-      }
-      const uint32_t b = sm.t2[lo];
-      ws.work[N][sm.base_work + j] = ((uint64_t)(sm.base_seg + lo) << 32) | (j - sm.t1[b]);
-    }
-    // 8192-key tiles: the scatter's items, child by child in work-item order
-    if constexpr (KMAX <= 1024) {
-      for (uint32_t j = t; j < ntiles; j += kBlock) {
-        uint32_t lo = 0, hi = nchild;  // invariant: hq[bucket(lo)] <= j
-        while (hi - lo > 1) {
-          uint32_t mid = (lo + hi) >> 1;
-          if (sm.hq[sm.t2[mid]] <= j) lo = mid; else hi = mid;
+    // work items and (8192-key tiles) scatter tiles, child by child in
+    // chunk order: a wave per child, its lanes over the child's entries
+    // (cheaper than a search per entry, a chain of dependent LDS reads)
+    for (uint32_t cc = wave(); cc < nchild; cc += kWaves) {
+      const uint32_t b = sm.t2[cc];
+      const uint32_t n = sm.h[b];
+      const uint32_t w0 = sm.t1[b];
+      const uint32_t nw_c = (uint32_t)((n + ch - 1) / ch);
+      const uint64_t segw = (uint64_t)(sm.base_seg + cc) << 32;
+      for (uint32_t j = lane(); j < nw_c; j += kWave) ws.work[N][sm.base_work + w0 + j] = segw | j;
+      if constexpr (KMAX <= 1024) {
+        if (nsub > 1) {
+          const uint32_t u0 = sm.hq[b], nt_c = (n + 8191u) >> 13;
+          for (uint32_t j = lane(); j < nt_c; j += kWave)
+            ws.tiles[N][sm.base_tile + u0 + j] = tile_entry(sm.base_seg + cc, j, nsub);
         }
-        const uint32_t b = sm.t2[lo];
-        ws.tiles[N][sm.base_tile + j] = tile_entry(sm.base_seg + lo, j - sm.hq[b], nsub);
       }
     }
   }
