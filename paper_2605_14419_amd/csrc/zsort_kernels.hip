@@ -1446,8 +1446,9 @@ struct ScatSmem {
 // A tile of T keys is ranked in registers; its keys then leave in cluster
 // order through LDS windows of SW keys (the whole tile where it fits), so
 // each cluster's run per tile is T / k keys long.
+// (a workgroup of 1024 threads is one per CU: its register budget is 128)
 template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
-__global__ void __launch_bounds__(SB, (ROUNDS <= 8 ? 4 : 2)) k_scatter(Ws ws, int L) {
+__global__ void __launch_bounds__(SB, (SB >= 1024 ? 1 : (ROUNDS <= 8 ? 4 : 2))) k_scatter(Ws ws, int L) {
   using P = typename PayT<PW>::T;
   using Sm = ScatSmem<KMAX, PW, ROUNDS, SB>;
   constexpr int NWV = Sm::NWV;
