@@ -996,16 +996,21 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   Ctl* c = ws.ctl;
   const int k = ws.p.k;
   const uint32_t cutoff = (uint32_t)ws.p.cutoff;
-  const uint64_t ch = (uint64_t)ws.p.chunk;
+  const uint32_t ch = (uint32_t)ws.p.chunk;   // (n + ch - 1 < 2^32: 32-bit divisions)
   const int S = L & 1, N = S ^ 1;
   const int t = threadIdx.x;
+  // the parent's fields in registers: stores to the children's records and
+  // the leaf lists would otherwise make the compiler load them again
+  const uint64_t sg_start = sg.start, sg_count = sg.count, sg_o = sg.o;
+  const double sg_m = sg.m, sg_sigma = sg.sigma, sg_zmin = sg.zmin;
+  const int32_t sg_kind = sg.kind;
 
   // exclusive cluster starts, and per child: index, chunk offset, scan row
   // offset, tile offset -- five scans in one pass
   for (int b = t; b < k; b += kBlock) {
     const uint32_t n = sm.h[b];
     const bool child = n > cutoff;
-    const uint32_t nch = child ? (uint32_t)((n + ch - 1) / ch) : 0u;
+    const uint32_t nch = child ? (n + ch - 1) / ch : 0u;
     sm.bst[b] = n;
     sm.t0[b] = child ? 1u : 0u;
     sm.t1[b] = nch;
@@ -1029,26 +1034,30 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   }
   uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
   for (int b = t; b < k; b += kBlock) gb[b] = sm.bst[b];
-  if (t == 0) {
-    sm.base_seg = nchild ? atomicAdd(&c->nseg[N], nchild) : 0u;
-    sm.base_work = nwork ? atomicAdd(&c->nwork[N], nwork) : 0u;
-    sm.base_status = nstat ? atomicAdd(&c->nstatus[N], nstat) : 0u;
-    sm.base_tile = ntiles ? atomicAdd(&c->ntile[N], ntiles) : 0u;
-    if (nchild) {
-      atomicMax(&c->max_level, (uint32_t)(L + 1));
-      if (sm.base_seg + nchild > ws.seg_cap) atomicOr(&c->error, ERR_SEGCAP);
-      if (sm.base_work + nwork > ws.work_cap) atomicOr(&c->error, ERR_WORKCAP);
-      if (sm.base_status + nstat > ws.status_cap) atomicOr(&c->error, ERR_STATUSCAP);
-      if (sm.base_tile + ntiles > ws.tile_cap && ntiles) atomicOr(&c->error, ERR_WORKCAP);
-    }
+  // the four list allocations in one atomic instruction (four lanes): the
+  // counters are shared by every workgroup of the level, so each round trip
+  // is a long one
+  if (t < 4) {
+    uint32_t* ctr = t == 0 ? &c->nseg[N] : (t == 1 ? &c->nwork[N] : (t == 2 ? &c->nstatus[N] : &c->ntile[N]));
+    const uint32_t v = t == 0 ? nchild : (t == 1 ? nwork : (t == 2 ? nstat : ntiles));
+    const uint32_t r = v ? atomicAdd(ctr, v) : 0u;
+    uint32_t* out = t == 0 ? &sm.base_seg : (t == 1 ? &sm.base_work : (t == 2 ? &sm.base_status : &sm.base_tile));
+    *out = r;
   }
   __syncthreads();
+  if (t == 0 && nchild) {
+    atomicMax(&c->max_level, (uint32_t)(L + 1));
+    if (sm.base_seg + nchild > ws.seg_cap) atomicOr(&c->error, ERR_SEGCAP);
+    if (sm.base_work + nwork > ws.work_cap) atomicOr(&c->error, ERR_WORKCAP);
+    if (sm.base_status + nstat > ws.status_cap) atomicOr(&c->error, ERR_STATUSCAP);
+    if (sm.base_tile + ntiles > ws.tile_cap && ntiles) atomicOr(&c->error, ERR_WORKCAP);
+  }
   const bool fits = sm.base_seg + nchild <= ws.seg_cap && sm.base_work + nwork <= ws.work_cap &&
                     sm.base_status + nstat <= ws.status_cap &&
                     (ntiles == 0 || sm.base_tile + ntiles <= ws.tile_cap);
   const double scale = (double)k / 4.0;
-  const bool parent_r = sg.kind == KIND_RMAP;
-  const bool parent_l = sg.kind == KIND_LMAP;  // children take their exact mean
+  const bool parent_r = sg_kind == KIND_RMAP;
+  const bool parent_l = sg_kind == KIND_LMAP;  // children take their exact mean
   if (fits) {
     for (int b = t; b < k; b += kBlock) {
       const uint32_t n = sm.h[b];
@@ -1056,24 +1065,24 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       const uint32_t idx = sm.base_seg + sm.t0[b];
       Seg& cs = ws.segs[N][idx];
       const bool crm = !(parent_l && ws.lm.sub) &&
-                       (parent_r || (L + 1 >= ws.p.max_zlevels) || (uint64_t)n == sg.count);
-      cs.start = sg.start + sm.bst[b];
+                       (parent_r || (L + 1 >= ws.p.max_zlevels) || (uint64_t)n == sg_count);
+      cs.start = sg_start + sm.bst[b];
       cs.count = n;
-      cs.o_parent = sg.o;
+      cs.o_parent = sg_o;
       double e = 0.0;
       if (!crm && !parent_l) {  // estimated mean of cluster b, parent's frame
         double q = ((double)b + 0.5) / scale;
-        q = q - sg.zmin;
-        q = q * sg.sigma;
-        e = q + sg.m;
+        q = q - sg_zmin;
+        q = q * sg_sigma;
+        e = q + sg_m;
       }
       cs.e = e;
       cs.depth = L + 1;
       cs.flags = crm ? F_RMAP : (parent_l ? F_ROOT : 0u);
-      cs.nchunks = (uint32_t)((n + ch - 1) / ch);
+      cs.nchunks = (n + ch - 1) / ch;
       cs.first_work = sm.base_work + sm.t1[b];
       cs.status_base = sm.base_status + sm.t2[b];
-      clear_arrivals(ws.arrive[N] + cs.status_base, cs.nchunks);
+      clear_arrivals(ws.arrive[N] + sm.base_status + sm.t2[b], (n + ch - 1) / ch);
       cs.parent = (int32_t)si;
       seg_clear_acc(cs);
       if (parent_l && ws.lm.sub) {
@@ -1097,20 +1106,40 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     // work items and (8192-key tiles) scatter tiles, child by child in
     // chunk order: a wave per child, its lanes over the child's entries
     // (cheaper than a search per entry, a chain of dependent LDS reads)
-    for (uint32_t cc = wave(); cc < nchild; cc += kWaves) {
-      const uint32_t b = sm.t2[cc];
-      const uint32_t n = sm.h[b];
-      const uint32_t w0 = sm.t1[b];
-      const uint32_t nw_c = (uint32_t)((n + ch - 1) / ch);
-      const uint64_t segw = (uint64_t)(sm.base_seg + cc) << 32;
-      for (uint32_t j = lane(); j < nw_c; j += kWave) ws.work[N][sm.base_work + w0 + j] = segw | j;
-      if constexpr (KMAX <= 1024) {
-        if (nsub > 1) {
-          const uint32_t u0 = sm.hq[b], nt_c = (n + 8191u) >> 13;
-          for (uint32_t j = lane(); j < nt_c; j += kWave)
-            ws.tiles[N][sm.base_tile + u0 + j] = tile_entry(sm.base_seg + cc, j, nsub);
-        }
+    // (first the children's offsets by child index, in t0 and t1, so that a
+    // wave finds a child's ranges with one round of independent LDS reads)
+    constexpr int CPT = (KMAX + kBlock - 1) / kBlock;
+    uint32_t ow[CPT], ou[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t cc = t + q * kBlock;
+      ow[q] = 0;
+      ou[q] = 0;
+      if (cc < nchild) {
+        const uint32_t b = sm.t2[cc];
+        ow[q] = sm.t1[b];
+        if constexpr (KMAX <= 1024) ou[q] = sm.hq[b];
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t cc = t + q * kBlock;
+      if (cc < nchild) {
+        sm.t0[cc] = ow[q];
+        sm.t1[cc] = ou[q];
+      }
+    }
+    __syncthreads();
+    for (uint32_t cc = wave(); cc < nchild; cc += kWaves) {
+      const bool last = cc + 1 == nchild;
+      const uint32_t w0 = sm.t0[cc], w1 = last ? nwork : sm.t0[cc + 1];
+      const uint32_t u0 = sm.t1[cc], u1 = last ? ntiles : sm.t1[cc + 1];
+      const uint64_t segw = (uint64_t)(sm.base_seg + cc) << 32;
+      for (uint32_t j = lane(); j < w1 - w0; j += kWave) ws.work[N][sm.base_work + w0 + j] = segw | j;
+      if (nsub > 1)
+        for (uint32_t j = lane(); j < u1 - u0; j += kWave)
+          ws.tiles[N][sm.base_tile + u0 + j] = tile_entry(sm.base_seg + cc, j, nsub);
     }
   }
   __syncthreads();
@@ -1150,7 +1179,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   for (uint32_t i = t; i < nb; i += kBlock) {
     if (!(bpos[i] >> 31)) continue;
     const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
-    const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
+    const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
     if (p1 - p0 <= wcap) ++my_small;
     else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
     else ++my_big;
@@ -1160,27 +1189,31 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   block_excl_sum3(mine, sm.shm, offs, tots);
   const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2];
   const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2];
-  if (t == 0) {
-    sm.base_leaf = nsmall ? atomicAdd(&c->nleafw[S], nsmall) : 0u;
-    sm.base_mid = nmid ? atomicAdd(&c->nleafm[S], nmid) : 0u;
-    sm.base_status = nbig ? atomicAdd(&c->nleaf[S], nbig) : 0u;  // (reused as the big-list base)
-    sm.st_groups += nsmall + nmid + nbig;
-    if (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
-        sm.base_status + nbig > ws.leaf_cap)
-      atomicOr(&c->error, ERR_LEAFCAP);
+  // the three leaf lists, likewise in one atomic instruction
+  if (t < 3) {
+    uint32_t* ctr = t == 0 ? &c->nleafw[S] : (t == 1 ? &c->nleafm[S] : &c->nleaf[S]);
+    const uint32_t v = t == 0 ? nsmall : (t == 1 ? nmid : nbig);
+    const uint32_t r = v ? atomicAdd(ctr, v) : 0u;
+    // (base_status is reused as the big-list base)
+    uint32_t* out = t == 0 ? &sm.base_leaf : (t == 1 ? &sm.base_mid : &sm.base_status);
+    *out = r;
   }
+  if (t == 0) sm.st_groups += nsmall + nmid + nbig;
   __syncthreads();
+  if (t == 0 && (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
+                 sm.base_status + nbig > ws.leaf_cap))
+    atomicOr(&c->error, ERR_LEAFCAP);
   if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
       sm.base_status + nbig <= ws.leaf_cap) {
     uint32_t os = sm.base_leaf + off_small, om = sm.base_mid + off_mid, ob = sm.base_status + off_big;
     for (uint32_t i = t; i < nb; i += kBlock) {
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
-      const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg.count;
+      const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
       const bool small = p1 - p0 <= wcap;
       const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
       Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
-      lf.start = (uint32_t)(sg.start + p0);
+      lf.start = (uint32_t)(sg_start + p0);
       lf.count = p1 - p0;
       lf.flags = 0;
       lf.src = (uint32_t)N;  // written by this level's scatter
@@ -1201,7 +1234,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
 
   // statistics and trace
   if (t == 0) {
-    sm.st_keys += sg.count;
+    sm.st_keys += sg_count;
     sm.st_segs += 1u;
   }
   if (ws.trace) {
