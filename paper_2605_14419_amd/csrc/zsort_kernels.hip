@@ -1131,10 +1131,35 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       }
     }
     __syncthreads();
+    // a child of at most kBlock entries is written by one thread, a larger
+    // one by a wave (a thread per child keeps every store independent)
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t cc = t + q * kBlock;
+      if (cc < nchild) {
+        const bool last = cc + 1 == nchild;
+        const uint32_t w0 = sm.t0[cc], w1 = last ? nwork : sm.t0[cc + 1];
+        const uint32_t u0 = sm.t1[cc], u1 = last ? ntiles : sm.t1[cc + 1];
+        if ((w1 - w0) + (u1 - u0) <= (uint32_t)kBlock) {
+          const uint64_t segw = (uint64_t)(sm.base_seg + cc) << 32;
+          uint64_t* wp = ws.work[N] + sm.base_work + w0;
+          for (uint32_t j = 0; j < w1 - w0; ++j) wp[j] = segw | j;
+          if (nsub > 1) {
+            uint64_t* tp = ws.tiles[N] + sm.base_tile + u0;
+            uint32_t ci = 0, sub = 0;
+            for (uint32_t j = 0; j < u1 - u0; ++j) {
+              tp[j] = segw | (ci << 3) | sub;   // tile_entry of tile j of the child
+              if (++sub == nsub) { sub = 0; ++ci; }
+            }
+          }
+        }
+      }
+    }
     for (uint32_t cc = wave(); cc < nchild; cc += kWaves) {
       const bool last = cc + 1 == nchild;
       const uint32_t w0 = sm.t0[cc], w1 = last ? nwork : sm.t0[cc + 1];
       const uint32_t u0 = sm.t1[cc], u1 = last ? ntiles : sm.t1[cc + 1];
+      if ((w1 - w0) + (u1 - u0) <= (uint32_t)kBlock) continue;
       const uint64_t segw = (uint64_t)(sm.base_seg + cc) << 32;
       for (uint32_t j = lane(); j < w1 - w0; j += kWave) ws.work[N][sm.base_work + w0 + j] = segw | j;
       if (nsub > 1)
