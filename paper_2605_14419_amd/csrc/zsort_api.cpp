@@ -493,6 +493,10 @@ hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t
   // ahead of the device.  Under stream capture every level is launched (each
   // kernel of an empty level exits at once).
   const bool paced = !c.level0_only && !capturing(st) && pacing_ready(w);
+  // (the last kernel of each level stores the next level's segment count in
+  // the pinned words; the event after it makes the store visible)
+  Ws wsp = ws;
+  wsp.h_nseg = paced ? w->h_nseg : nullptr;
   for (int L = L0; L < levels && e == hipSuccess; ++L) {
     if (paced && L >= 2) {
       e = hipEventSynchronize(w->lvl_ev[L - 2]);
@@ -501,13 +505,9 @@ hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t
     }
     for (int sid = 0; sid < zs::NSTAGES && e == hipSuccess; ++sid) {
       if (c.level0_only && (sid == zs::STAGE_LOCAL || sid == zs::STAGE_LOCAL_HARD)) continue;
-      e = stage(w, ws, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
+      e = stage(w, wsp, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
     }
-    if (paced && e == hipSuccess) {
-      e = hipMemcpyAsync(&w->h_nseg[L + 1], &ws.ctl->nseg[(L + 1) & 1], sizeof(uint32_t),
-                         hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[L], st);
-    }
+    if (paced && e == hipSuccess) e = hipEventRecord(w->lvl_ev[L], st);
   }
   return e;
 }

@@ -221,6 +221,8 @@ struct Ws {
   TraceRec* trace;       // may be null
   uint32_t* trace_hist;
   uint32_t trace_cap, trace_hist_cap;
+  uint32_t* h_nseg;      // pinned host words, or null: the last kernel of level L stores
+                         // there the segment count of level L + 1 (0 after an error)
   uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
   Params p;
   LMap lm;

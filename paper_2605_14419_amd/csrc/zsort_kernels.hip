@@ -2020,6 +2020,11 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
   using Sm = LocSmem<PW>;
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
+  // the host paces the levels by the next level's segment count, stored
+  // straight into its pinned memory (no copy in the stream)
+  if (ws.h_nseg && blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&ws.h_nseg[L + 1], call_failed(c) ? 0u : c->nseg[(L + 1) & 1],
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (call_failed(c)) return;
   const int S = L & 1;
   const uint32_t nh = min(c->nhard[S], ws.leaf_cap);
