@@ -215,6 +215,23 @@ def test_cutoff_4096_vs_oracle(name, pw):
         assert np.array_equal(p, op)
 
 
+@pytest.mark.parametrize("nch,chunk,tile", [(2, 2048, 2048), (8, 2048, 2048), (9, 2048, 2048),
+                                           (64, 2048, 2048), (65, 2048, 2048), (257, 2048, 2048),
+                                           (1025, 2048, 2048), (65, 16384, 8192),
+                                           (300, 32768, 8192)])
+def test_cross_chunk_scan_unit_boundaries_vs_oracle(nch, chunk, tile):
+    # the root's chunks fall into scan units of 8..256 chunks (a power of two
+    # near sqrt(nch)); counts just at and past unit boundaries, ragged tail
+    n = nch * chunk - 777
+    x, idx = synth.make("normal", n)
+    cfg = dict(k=256, cutoff=2048, max_zlevels=8, chunk=chunk, tile=tile)
+    say("case scan units", nch, chunk, tile)
+    k, p, st = gpu_sort(x, idx, cfg)
+    assert st["device_error"] == 0
+    ok, oi, _ = oracle.sort(x, idx, k=256, cutoff=2048, max_zlevels=8)
+    assert np.array_equal(k, ok) and np.array_equal(p, oi)
+
+
 def test_profiling_one_kernel_kind_leaves_the_sort_unchanged():
     x, idx = synth.make("lognormal", 300_000)
     ok, oi, _ = oracle.sort(x, idx, **{kk: CFG[kk] for kk in ("k", "cutoff", "max_zlevels")})
