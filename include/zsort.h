@@ -153,7 +153,8 @@ size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
  *   levels            number of recursion levels that held work
  *   device_error      0, or bits: 1 segment list, 2 work list, 4 leaf list,
  *                     8 scan rows full, 16 scan-row wait limit,
- *                     0x100 malformed segment offsets
+ *                     32 a scatter destination outside its segment (never
+ *                     with consistent counts), 0x100 malformed segment offsets
  *   keys_per_level    keys distributed at each level
  *   segs_per_level    subproblems distributed at each level
  *   mkeys_per_level   keys whose moments were taken at each level
