@@ -324,9 +324,11 @@ def roofline(kt, stats, pw, steps, traffic_file, cfg):
     if os.path.exists(traffic_file):
         with open(traffic_file) as fh:
             tr = json.load(fh)
-        same_cfg = all(tr.get("config", {}).get(x) == cfg.get(x) for x in ("k", "tile", "chunk"))
-        if tr.get("kernel_hash") == kernel_source_hash() and tr.get("stage") == dom and same_cfg:
-            traffic = tr.get("bytes_per_launch")
+        if tr.get("kernel_hash") == kernel_source_hash():
+            for ent in tr.get("entries", []):
+                if ent.get("stage") == dom and all(ent.get("config", {}).get(x) == cfg.get(x)
+                                                   for x in ("k", "tile", "chunk", "cutoff")):
+                    traffic = ent.get("bytes_per_launch")
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
@@ -397,7 +399,8 @@ def summarize_profiles(d, workload, cfg):
               "|---|---|---|---|"]
     for st, (ns, c) in sorted(per_stage.items(), key=lambda x: -x[1][0]):
         lines.append(f"| {st} | {c} | {ns / 1e6:.3f} | {ns / c / 1e3:.1f} |")
-    with open(os.path.join(out_dir, f"kernels_{workload}.md"), "w") as fh:
+    tag = f"{workload}_k{cfg['k']}_c{cfg['cutoff']}_ch{cfg['chunk']}_t{cfg['tile']}"
+    with open(os.path.join(out_dir, f"kernels_{tag}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     # HBM traffic, calibrated on the copy probe (1 GiB read + 1 GiB written per copy)
     def counter(sub, cname):
@@ -441,15 +444,25 @@ def summarize_profiles(d, workload, cfg):
         gbs = (fb + wb) / (us * 1e-6) / 1e9 if us > 0 else 0.0
         lines.append(f"| {st} | {fetch[st][1]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} "
                      f"| {us:.1f} | {gbs:.0f} |")
-    with open(os.path.join(out_dir, f"traffic_{workload}.md"), "w") as fh:
+    with open(os.path.join(out_dir, f"traffic_{tag}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     dom = max(per_stage, key=lambda s: per_stage[s][0])
-    with open(os.path.join(out_dir, f"traffic_{workload}.json"), "w") as fh:
-        json.dump({"kernel_hash": kernel_source_hash(), "stage": dom, "config": cfg,
-                   "bytes_per_launch": round(traffic.get(dom, 0.0)),
-                   "per_stage_bytes_per_launch": {k: round(v) for k, v in traffic.items()},
-                   "fetch_factor": ff, "write_factor": wf}, fh, indent=1)
-    print(f"wrote kernels_{workload}.md, traffic_{workload}.md/.json (dominant {dom})")
+    # one entry per configuration (the autotuner's pick can differ between
+    # runs); entries taken with other kernel sources are dropped
+    jpath = os.path.join(out_dir, f"traffic_{workload}.json")
+    entries = []
+    if os.path.exists(jpath):
+        with open(jpath) as fh:
+            old = json.load(fh)
+        if old.get("kernel_hash") == kernel_source_hash():
+            entries = [e for e in old.get("entries", []) if e.get("config") != cfg]
+    entries.append({"stage": dom, "config": cfg, "summary": f"traffic_{tag}.md",
+                    "bytes_per_launch": round(traffic.get(dom, 0.0)),
+                    "per_stage_bytes_per_launch": {k: round(v) for k, v in traffic.items()},
+                    "fetch_factor": ff, "write_factor": wf})
+    with open(jpath, "w") as fh:
+        json.dump({"kernel_hash": kernel_source_hash(), "entries": entries}, fh, indent=1)
+    print(f"wrote kernels_{tag}.md, traffic_{tag}.md, traffic_{workload}.json (dominant {dom})")
 
 
 def measured_copy_gbs(dev, reps=5):
