@@ -2184,7 +2184,7 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
     for (int q = 0; q < TW; ++q) big |= sh[q];
     team_sync<TW>();
     uint32_t total;
-    base = block_excl_sum(tsum, sh, &total);
+    base = block_excl_sum<TW * kWave>(tsum, sh, &total);
   }
   if (big) {
     team_sync<TW>();
@@ -2419,20 +2419,22 @@ __global__ void __launch_bounds__(kWave) k_local_mid(Ws ws, int L) {
 }
 
 // Block jobs of kBlockCap < n <= kBigCap keys (cutoffs above kBlockCap): a
-// workgroup with 16 keys per thread, in a kernel of its own so that the main
-// kernel's LDS (and with it its occupancy) stays sized for kBlockCap.  The
-// main kernel counts these groups in its statistics.
+// workgroup of 512 threads with 8 keys each, in a kernel of its own so that
+// the main kernel's LDS (and with it its occupancy) stays sized for
+// kBlockCap.  The main kernel counts these groups in its statistics.
+constexpr int kBigThreads = 512;
+constexpr int kBigWaves = kBigThreads / kWave;
 template <int PW>
 struct BigSmem {
   uint64_t k[kBigCap];
   typename PayT<PW>::T pay[PW ? kBigCap : 1];
   uint32_t cnt[kBigCap / 2];
-  uint64_t rmin[kWaves], rmax[kWaves];
-  uint32_t sh[kWaves + 2];
+  uint64_t rmin[kBigWaves], rmax[kBigWaves];
+  uint32_t sh[kBigWaves + 2];
 };
 
 template <int PW>
-__global__ void __launch_bounds__(kBlock) k_local_big(Ws ws, int L) {
+__global__ void __launch_bounds__(kBigThreads) k_local_big(Ws ws, int L) {
   __shared__ BigSmem<PW> sm;
   Ctl* c = ws.ctl;
   if (call_failed(c)) return;
@@ -2445,7 +2447,7 @@ __global__ void __launch_bounds__(kBlock) k_local_big(Ws ws, int L) {
     const Leaf lf = ws.leaves[S][g];
     const uint32_t n = lf.count;
     if ((lf.flags & LF_COPY) || n <= (uint32_t)kBlockCap || n > (uint32_t)kBigCap) continue;
-    const bool ok = fast_sort<PW, kWaves, kBigCap / kBlock>(
+    const bool ok = fast_sort<PW, kBigWaves, kBigCap / kBigThreads>(
         sm.k, sm.pay, sm.cnt, sm.rmin, sm.rmax, sm.sh, ws.keys[lf.src], ws.pay[lf.src], dst, pdst,
         lf.start, n, (uint32_t)t);
     if (!ok && t == 0) push_hard(ws, S, lf);
@@ -2488,7 +2490,7 @@ static int mid_grid() {
 template <int PW>
 static int big_grid() {
   static int g = 0;
-  if (g == 0) g = resident_grid((const void*)k_local_big<PW>, kBlock);
+  if (g == 0) g = resident_grid((const void*)k_local_big<PW>, kBigThreads);
   return g;
 }
 
@@ -2517,7 +2519,7 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
       hipLaunchKernelGGL((k_local<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       hipLaunchKernelGGL((k_local_mid<PW>), dim3(mid_grid<PW>()), dim3(kWave), 0, st, ws, L);
       if (ws.p.cutoff > kBlockCap)  // groups above kBlockCap exist only then
-        hipLaunchKernelGGL((k_local_big<PW>), dim3(big_grid<PW>()), dim3(kBlock), 0, st, ws, L);
+        hipLaunchKernelGGL((k_local_big<PW>), dim3(big_grid<PW>()), dim3(kBigThreads), 0, st, ws, L);
       break;
     default:
       hipLaunchKernelGGL((k_local_hard<PW>), dim3(grid), dim3(kBlock), 0, st, ws, L);
