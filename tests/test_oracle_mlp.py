@@ -191,3 +191,83 @@ def test_training_reduces_the_loss_on_a_mixture_sample():
     # still monotone after training (projection)
     f = np.array([oracle.mlp_forward(p2, float(v)) for v in np.linspace(0, 1, 5001)])
     assert np.all(np.diff(f) >= 0)
+
+
+# ---------------------------------------------------------------------------
+# Adam over several steps: a hand-derived golden (tests/golden/adam_three_steps.json)
+# ---------------------------------------------------------------------------
+import json
+import os
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adam_three_steps.json")
+
+
+def _f32_ulp(v):
+    v = np.float32(v)
+    return float(np.spacing(np.abs(v))) if v != 0 else float(np.spacing(np.float32(0)))
+
+
+def _adam_case(case):
+    p = np.zeros(oracle.MLP_NP, dtype=np.float64)
+    free = [oracle.B3]
+    if "W3_0_init" in case:
+        p[oracle.W3] = case["W3_0_init"]
+        p[oracle.B2] = 1.0
+        free.append(oracle.W3)
+    u = np.array([0.1, 0.2, 0.3, 0.4])
+    y = np.array(case["targets"], dtype=np.float64)
+    return p, u, y, free
+
+
+@pytest.mark.parametrize("name", ["case_A", "case_B"])
+def test_adam_three_steps_match_hand_derivation(name):
+    """Parameters after 1, 2 and 3 Adam steps equal the values worked out by
+    hand from the published algorithm (running powers of beta1/beta2, bias
+    correction of each moment, minibatch t mod nb, binary32 rounding and the
+    projection of weights, with the moments kept across a projection)."""
+    g = json.load(open(GOLDEN))
+    case = g[name]
+    p0, u, y, free = _adam_case(case)
+    for st in case["steps"]:
+        t = st["t"]
+        p, lf, ll = oracle.mlp_train(p0, u, y, steps=t, batches=case["batches"], lr=g["lr"])
+        want = {oracle.B3: st["b3"]}
+        if "W3_0" in st:
+            want[oracle.W3] = st["W3_0"]
+        for idx, v in want.items():
+            # binary32 parameters: the hand value rounded to binary32 (one ulp
+            # of slack for the last bit of the unrounded step)
+            assert abs(p[idx] - v) <= _f32_ulp(v), (name, t, idx, p[idx], v)
+        # every parameter without a gradient is untouched
+        other = np.ones(oracle.MLP_NP, dtype=bool)
+        other[free] = False
+        assert np.array_equal(p[other], oracle._par(p0)[other]), (name, t)
+        assert abs(lf - case["steps"][0]["loss_before"]) <= 1e-12 * case["steps"][0]["loss_before"]
+        assert abs(ll - st["loss_before"]) <= 1e-9 * st["loss_before"] + 1e-15, (name, t, ll)
+    if name == "case_B":
+        # projected to exactly 0 after step 1, positive again after step 2
+        p1, _, _ = oracle.mlp_train(p0, u, y, steps=1, batches=1, lr=g["lr"])
+        assert p1[oracle.W3] == 0.0 and p1[oracle.B3] < 0.0
+
+
+# ---------------------------------------------------------------------------
+# key normalisation u(x) = (x - smin) / (smax - smin) inside the range
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("smin,smax,x,want", [
+    (0, 2**40, 2**39, 0.5),
+    (0, 2**40, 2**38, 0.25),
+    (0, 2**40, 3 * 2**38, 0.75),
+    (2**20, 2**20 + 2**40, 2**20 + 2**39, 0.5),
+    (10, 110, 35, 0.25),
+    (10, 110, 60, 0.5),
+    (10, 110, 11, 0.01),
+    (2**63, 2**64 - 1, 2**63 + 2**62, 0.5),
+    (5, 7, 6, 0.5),
+])
+def test_norm_interior_closed_forms(smin, smax, x, want):
+    """Inside (smin, smax) the normalised key is the exact ratio of the key's
+    offset from smin to the range, correctly rounded; the ends clamp."""
+    assert oracle.mlp_norm(x, smin, smax) == want
+    assert oracle.mlp_norm(smin, smin, smax) == 0.0
+    assert oracle.mlp_norm(smax, smin, smax) == 1.0
+    assert oracle.mlp_norm(max(smin, 1) - 1, smin, smax) == 0.0
