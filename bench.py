@@ -75,20 +75,8 @@ def to_device(keys_np, pay_np, dev):
 
 def verify_on_device(k_in, k_out, p_out):
     """sorted (unsigned), payload is a permutation carrying its key, stable"""
-    import torch
-    sign = torch.tensor(-(2**63), dtype=torch.int64, device=k_out.device)
-    ks = k_out ^ sign  # unsigned order as signed order
-    assert bool((ks[1:] >= ks[:-1]).all()), "keys not sorted"
-    if p_out is None:
-        return
-    idx = p_out.long() & 0xFFFFFFFF if p_out.dtype == torch.int32 else p_out.long()
-    n = k_out.numel()
-    seen = torch.zeros(n, dtype=torch.int32, device=k_out.device)
-    seen.index_fill_(0, idx, 1)
-    assert int(seen.sum()) == n, "payload not a permutation"
-    assert bool((k_in[idx] == k_out).all()), "key does not match its index"
-    eq = ks[1:] == ks[:-1]
-    assert bool((idx[1:][eq] > idx[:-1][eq]).all()), "equal keys out of input order"
+    from tests.invariants import check_stable_sorted_device
+    check_stable_sorted_device(k_in, k_out, p_out)
 
 
 def run_workload(spec, steps, warmup, cfg, dev, profile=True):
@@ -234,11 +222,11 @@ def run_batched(steps, warmup, dev, nseg=4096):
     l_ms = ev0.elapsed_time(ev1)
     log(f"[bench] batched graph {g_ms:.3f} ms/step, loop {l_ms:.1f} ms "
         f"(host {1e3 * (time.time() - t0):.1f} ms)")
-    assert np.array_equal(lk.cpu().numpy().view(np.uint64), gk), "loop and graph disagree"
-    for i in range(0, nseg, max(1, nseg // 16)):  # spot-check segments
-        a, b = offs[i], offs[i + 1]
-        seg = gk[a:b]
-        assert np.all(seg[1:] >= seg[:-1])
+    assert np.array_equal(lk.cpu().numpy().view(np.uint64), gk), "loop and graph keys disagree"
+    assert torch.equal(lp, bufs[-1][1]), "loop and graph payloads disagree"
+    # every segment sorted, stable and a permutation of its own keys
+    from tests.invariants import check_segmented_stable_sorted_device
+    check_segmented_stable_sorted_device(base_k, bufs[-1][0], bufs[-1][1], toff)
     del bufs
     torch.cuda.empty_cache()
     return {"workload": f"{nseg} arrays, lognormal lengths (median 2e4, [100, 1e6]), "
@@ -518,21 +506,38 @@ def cpu_library_reference(keys, budget_s=3.0):
 
 
 def cpu_baseline(keys, cfg, budget_s):
+    """The oracle as it stands, single-threaded, on the first 10^7 keys of the
+    workload: with Algorithm 1's own settings (k = floor(sqrt(n)) clusters per
+    pass, insertion sort at <= 96 keys) as the baseline, and with the GPU's
+    configuration beside it (half the budget each)."""
     import oracle
     ns = min(keys.size, 10**7)
     sample = np.ascontiguousarray(keys[:ns])
     idx = np.arange(ns, dtype=np.uint32)
-    reps, t0 = 0, time.time()
-    while True:
-        oracle.sort(sample, idx, k=cfg["k"], cutoff=cfg["cutoff"], max_zlevels=cfg["max_zlevels"])
-        reps += 1
-        el = time.time() - t0
-        if el >= budget_s or reps >= 20:
-            break
-    return {"value": round(ns * reps / el / 1e9, 5), "unit": "GKeys/s", "cores": 1,
-            "kind": "oracle", "cpu_model": cpu_model(),
+
+    def timed(par):
+        reps, t0 = 0, time.time()
+        while True:
+            oracle.sort(sample, idx, k=par["k"], cutoff=par["cutoff"],
+                        max_zlevels=par["max_zlevels"])
+            reps += 1
+            el = time.time() - t0
+            if el >= budget_s / 2 or reps >= 20:
+                return round(ns * reps / el / 1e9, 5), reps, el
+
+    paper = oracle.paper_params(ns)
+    v, reps, el = timed(paper)
+    vg, repg, elg = timed(cfg)
+    return {"value": v, "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+            "settings": f"Algorithm 1: k = floor(sqrt(n)) = {paper['k']} clusters per pass, "
+                        f"insertion sort at <= {paper['cutoff']} keys",
+            "cpu_model": cpu_model(),
             "sample": f"first {ns} keys of the same array, u32 index payload, {reps} rep(s), "
-                      f"{el:.1f}s single-threaded"}
+                      f"{el:.1f}s single-threaded",
+            "gpu_config": {"value": vg, "unit": "GKeys/s",
+                           "settings": f"the GPU's configuration: k {cfg['k']}, cutoff "
+                                       f"{cfg['cutoff']}, max_zlevels {cfg['max_zlevels']}",
+                           "sample": f"the same sample, {repg} rep(s), {elg:.1f}s"}}
 
 
 def main():
@@ -552,6 +557,9 @@ def main():
                          "autotuner's, e.g. k=256,cutoff=2048,chunk=32768,tile=4096")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 csv output and exit")
+    ap.add_argument("--workload", default="primary",
+                    help="workload of the main line: primary (lognormal + u64 index) or one of "
+                         + ", ".join(EXTRAS) + " (profiling runs)")
     args = ap.parse_args()
     if args.summarize_profiles:
         if not args.config:
@@ -560,7 +568,8 @@ def main():
         for kv in args.config.split(","):
             a, b = kv.split("=")
             pc[a.strip()] = int(b)
-        summarize_profiles(args.summarize_profiles, PRIMARY["workload"], pc)
+        wl = PRIMARY if args.workload == "primary" else EXTRAS[args.workload]
+        summarize_profiles(args.summarize_profiles, wl["workload"], pc)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -573,7 +582,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     zs.lib()  # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
-    spec = dict(PRIMARY, n=args.n)
+    spec = dict(PRIMARY if args.workload == "primary" else EXTRAS[args.workload])
+    if args.workload == "primary":
+        spec["n"] = args.n
 
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.int64, device=dev).fill_(7)
@@ -634,7 +645,8 @@ def main():
                         z / extras[name]["ms_per_step_model_reused"], 3)
                 continue
             es = EXTRAS[name]
-            ek, ems, est, ekt, ecfg = run_workload(es, max(3, args.steps // 2), 1, None, dev)
+            esteps = max(3, args.steps // 2)
+            ek, ems, est, ekt, ecfg = run_workload(es, esteps, 1, None, dev)
             del ek
             epw = es["payload_bytes"]
             extras[name] = {
@@ -646,6 +658,9 @@ def main():
                 "levels": est["levels"], "config": ecfg,
                 "kernel_ms_per_step": {s: round(est["kernel_ms_per_step"][s][0], 4)
                                        for s in STAGES},
+                "roofline": roofline(ekt, est, epw, esteps,
+                                     os.path.join(ROOT, "profiles",
+                                                  f"traffic_{es['workload']}.json"), ecfg),
             }
     out["extras"] = extras
     if not args.no_cpu_baseline:

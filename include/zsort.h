@@ -19,8 +19,13 @@
  *     unique).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *     on it and the call returns without waiting for the device, except that
- *     the first call at a new problem size allocates the workspace
- *     (hipMalloc, which synchronises the device).
+ *     a call whose problem size needs more workspace than the stream has
+ *     allocates it (hipMalloc, which synchronises the device).  While the
+ *     stream is being captured into a hipGraph a call never allocates: it
+ *     runs in the workspace the stream has (a new problem size is laid out
+ *     inside it) or returns ZSORT_ECAPTURE.  zsort_set_workspace hands the
+ *     library caller-owned memory instead, so that a caller can capture any
+ *     shape that fits it.
  *   - Limits: 1 <= n <= 2^31 - 1 keys per call (n <= 1 is a no-op that
  *     returns ZSORT_OK).  Buffers must not overlap.
  *   - Errors are returned as negative status codes; nothing throws across the
@@ -48,6 +53,19 @@ enum {
   ZSORT_EUNSUPPORTED = -5,  /* configuration not built into this library */
   ZSORT_EDEVICE = -6        /* a device-side limit was hit (only from synchronous calls) */
 };
+
+/*
+ * The operation every sorting entry point performs (the paper's Section III,
+ * problem statement and stability; Algorithm 1): the unique stable order of
+ * the keys, computed by recursive distribution -- exact moments of each
+ * subproblem (Algorithm 1's sum/minimum and variance loops), the z-score map
+ * of Eq. (1) with the clip of the cluster definition, histogram, exclusive
+ * prefix and stable scatter into one array separated by offsets (Algorithm
+ * 1's distribution loops), recursion with the estimated mean of the
+ * recursive phase for clusters above the cutoff, identical-key subproblems
+ * finished at once (duplicate handling, Section III), and small clusters
+ * sorted locally (Algorithm 1's insertion-sort step, here an in-LDS sort).
+ */
 
 /*
  * Tuning of the distribution.  k and cutoff change the recursion tree (and
@@ -93,21 +111,26 @@ typedef struct zsort_config {
   int32_t reserved[2];
 } zsort_config;
 
-/* Fills cfg with the defaults above.  Returns ZSORT_OK or ZSORT_EINVAL (null). */
+/* Fills cfg with the defaults above (k, the cutoff and the recursion depth
+ * are the parameters of Algorithm 1 and of the choice of k in Section III).
+ * Returns ZSORT_OK or ZSORT_EINVAL (null). */
 int zsort_default_config(zsort_config* cfg);
 
 /*
- * Autotuner: times candidate configurations (k in {256, 512, 1024}; (tile,
- * chunk) in {(2048, 16384), (4096, 32768), (8192, 8192), (8192, 32768)};
- * cutoff in {1024, 2048, 4096}) on a scratch copy of keys/payload (device buffers,
- * left unchanged; seg_offsets may be NULL for a single array) and remembers
- * the fastest for the shape class (n rounded up to a power of two, payload
- * width, single or segmented).
+ * Autotuner (an extension; the paper chooses k by the sensitivity study of
+ * Section III's choice of k and its table of alpha values): times candidate
+ * configurations (k in {256, 512, 1024}; (tile, chunk) in {(2048, 16384),
+ * (4096, 32768), (8192, 8192), (8192, 32768)}; cutoff in {1024, 2048, 4096})
+ * on a scratch copy of keys/payload (device buffers, left unchanged;
+ * seg_offsets may be NULL for a single array) and remembers the fastest that
+ * ran within the device's limits (device_error 0) for the shape class (n
+ * rounded up to a power of two, payload width, single or segmented).
  * Later calls of that class with cfg == NULL use it.  If the class is already
  * known no timing is done.  cache_path (may be NULL) names a text file of
  * tuned entries that is read first and rewritten afterwards.  best (host, may
  * be NULL) receives the chosen configuration.  Synchronous; allocates scratch
- * memory for the copies.
+ * memory for the copies.  The winner's output is checked to be sorted before
+ * it is remembered (single arrays); ZSORT_EDEVICE if no candidate passes.
  */
 int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes, size_t n,
                    const int64_t* seg_offsets, int32_t num_segments, const char* cache_path,
@@ -115,22 +138,30 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
 
 /*
  * Stable sort of keys[0, n) with an optional u32 payload (payload may be
- * NULL).  The default configuration is used.
+ * NULL); Algorithm 1 with the mapping of Eq. (1), Section III.  The tuned
+ * configuration of the shape class (zsort_autotune), else the defaults.
+ * keys: n u64, ascending unsigned on return; payload: n u32 moved with their
+ * keys.  Errors: ZSORT_EINVAL (null keys with n > 1, n >= 2^31),
+ * ZSORT_ENOMEM / ZSORT_EHIP / ZSORT_ECAPTURE as above.
  */
 int zsort_stable(uint64_t* keys, uint32_t* payload, size_t n, void* stream);
 
-/* As zsort_stable with a u64 payload (may be NULL). */
+/* As zsort_stable with a u64 payload (may be NULL): Algorithm 1, Eq. (1). */
 int zsort_stable_p64(uint64_t* keys, uint64_t* payload, size_t n, void* stream);
 
 /*
- * General form: payload_bytes is 0 (payload ignored, may be NULL), 4 or 8;
- * cfg may be NULL (defaults).
+ * General form of zsort_stable (Algorithm 1, Eq. (1), Section III):
+ * payload_bytes is 0 (payload ignored, may be NULL), 4 or 8; cfg may be NULL
+ * (tuned entry of the shape class, else the defaults); ZSORT_EINVAL for a
+ * configuration outside the ranges above.
  */
 int zsort_stable_ex(uint64_t* keys, void* payload, int payload_bytes, size_t n,
                     const zsort_config* cfg, void* stream);
 
 /*
- * Batched form: num_segments independent arrays laid end to end in keys[0, n);
+ * Batched form (an extension: Algorithm 1 applied to each of many arrays,
+ * whose recursions run level by level together): num_segments independent
+ * arrays laid end to end in keys[0, n);
  * segment i is [seg_offsets[i], seg_offsets[i+1]).  seg_offsets is a DEVICE
  * array of num_segments + 1 int64 with seg_offsets[0] = 0,
  * seg_offsets[num_segments] = n and non-decreasing entries (empty segments
@@ -144,12 +175,44 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
                            const int64_t* seg_offsets, int32_t num_segments,
                            const zsort_config* cfg, void* stream);
 
-/* Device bytes of workspace a call of this shape needs (0 if invalid). */
+/* Device bytes of workspace a call of this shape needs (0 if invalid): the
+ * ping-pong partner of keys and payload (Algorithm 1's second array), the
+ * recursion's lists and the histogram rows.  cfg NULL: the configuration such
+ * a call would use (the tuned entry of the shape class, else the defaults).
+ * Host-only; no device is touched. */
 size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
                              const zsort_config* cfg);
 
 /*
- * Statistics of the last call on `stream` (synchronises that stream).
+ * Caller-owned workspace for the calls on `stream` (the memory of Algorithm
+ * 1's second array and of the recursion's lists).  d_ws is DEVICE memory of
+ * `bytes` bytes, 256-byte aligned and at least a control block in size; it
+ * stays owned by the caller, who keeps it alive and unused by anything else
+ * until another zsort_set_workspace on that stream (or zsort_release).  From
+ * then on no call on the stream allocates: a problem whose
+ * zsort_workspace_bytes exceeds `bytes` returns ZSORT_ENOMEM, so a caller can
+ * capture zsort_stable_* into a graph of its own at any size that fits.
+ * d_ws NULL with bytes 0 returns the stream to library-allocated memory.  The
+ * library's own buffer of the stream, if any, is freed (synchronises the
+ * device).  Enqueues a clear of the control block on `stream`.  Errors:
+ * ZSORT_EINVAL (misaligned or too small, or NULL with bytes > 0),
+ * ZSORT_ECAPTURE (the stream is being captured).  The learned form keeps its
+ * own buffers (and is not capturable).
+ */
+int zsort_set_workspace(void* d_ws, size_t bytes, void* stream);
+
+/*
+ * Allocation limit for tests of the out-of-memory path: every device
+ * allocation the library would make that is larger than max_bytes fails as
+ * if the device were out of memory (the call returns ZSORT_ENOMEM).  0 (the
+ * default) removes the limit.  Host-only.
+ */
+int zsort_set_alloc_limit(size_t max_bytes);
+
+/*
+ * Statistics of the last call on `stream` (synchronises that stream): the
+ * recursion of Algorithm 1 as it ran, level by level (Section III's depth
+ * analysis counts these levels).
  *   levels            number of recursion levels that held work
  *   device_error      0, or bits: 1 segment list, 2 work list, 4 leaf list,
  *                     8 scan rows full, 16 scan-row wait limit,
@@ -184,7 +247,8 @@ typedef struct zsort_stats {
 int zsort_get_last_stats(void* stream, zsort_stats* out /* host */);
 
 /*
- * Parity/debug entry: one distribution pass of the root (moments, statistics,
+ * Parity/debug entry: one distribution pass of the root (Algorithm 1 up to the
+ * scatter, Eq. (1); moments, statistics,
  * histogram, scan, stable scatter), without recursion.  The resulting cluster
  * array (Algorithm 1's single array separated by offsets) is copied to
  * out_keys / out_payload (device, n elements; out_payload may be NULL when
@@ -217,7 +281,8 @@ typedef struct zsort_trace_rec {
 } zsort_trace_rec;
 
 /*
- * zsort_stable_ex that also records every subproblem (host buffers; records
+ * zsort_stable_ex that also records every subproblem (the recursion of
+ * Section III's recursive phase, one record per call of zsortRec) (host buffers; records
  * in no particular order).  counts[0] = records produced (may exceed
  * trace_cap), counts[1] = histogram words stored.  Synchronous; returns
  * ZSORT_EDEVICE if a device-side limit was hit.
@@ -227,7 +292,8 @@ int zsort_stable_traced(uint64_t* keys, void* payload, int payload_bytes, size_t
                         uint32_t* hist, int64_t hist_cap, int64_t counts[2], void* stream);
 
 /*
- * Per-kernel device time.  Between zsort_profile_begin(stream) and
+ * Per-kernel device time (measurement; not part of the method).  Between
+ * zsort_profile_begin(stream) and
  * zsort_profile_end(stream, out) every kernel the library launches on
  * `stream` is bracketed by a pair of hipEvents recorded on that same stream;
  * _end synchronises the stream and sums the elapsed times per kernel kind:
@@ -392,7 +458,8 @@ int zsort_mlp_grad(const zsort_mlp_params* params, const uint64_t* sorted_sample
 int zsort_mlp_train(zsort_mlp_params* params, const uint64_t* sorted_sample, size_t m, int32_t steps,
                     int32_t batches, double lr, double* losses_out, void* stream);
 
-/* Frees every cached workspace (synchronises the device). */
+/* Frees every workspace the library allocated (caller workspaces are left
+ * alone) and drops cached graphs (synchronises the device). */
 int zsort_release(void);
 
 /* Last hipError_t seen by the library (0 if none). */

@@ -24,7 +24,7 @@ EXPORTED = [
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
     "zsort_strerror", "zsort_profile_begin", "zsort_profile_begin_stages", "zsort_profile_end",
-    "zsort_autotune",
+    "zsort_autotune", "zsort_set_workspace", "zsort_set_alloc_limit",
     "zsort_default_learned_config", "zsort_stable_learned", "zsort_learned_sample",
     "zsort_mlp_forward", "zsort_mlp_thresholds", "zsort_mlp_init", "zsort_mlp_grad",
     "zsort_mlp_train",
@@ -117,6 +117,8 @@ def lib():
         L.zsort_stable_ex.argtypes = [P, P, I, Z, P, P]
         L.zsort_stable_segmented.argtypes = [P, P, I, Z, P, ctypes.c_int32, P, P]
         L.zsort_workspace_bytes.argtypes = [Z, I, ctypes.c_int32, P]
+        L.zsort_set_workspace.argtypes = [P, Z, P]
+        L.zsort_set_alloc_limit.argtypes = [Z]
         L.zsort_workspace_bytes.restype = Z
         L.zsort_get_last_stats.argtypes = [P, P]
         L.zsort_debug_level0.argtypes = [P, P, I, Z, P, P, P, P]
@@ -234,6 +236,25 @@ def zsort_stable_segmented(keys, seg_offsets, payload=None, cfg=None, stream=Non
 
 def zsort_workspace_bytes(n, payload_bytes=4, num_segments=0, cfg=None) -> int:
     return int(lib().zsort_workspace_bytes(n, payload_bytes, num_segments, _cfg(cfg)))
+
+
+def zsort_set_workspace(buf=None, stream=None):
+    """Hand the library caller-owned device memory (a CUDA tensor, kept alive
+    by the caller) as the workspace of `stream`; None returns the stream to
+    library-allocated memory."""
+    if buf is None:
+        _check("zsort_set_workspace", lib().zsort_set_workspace(None, 0, _stream(stream)))
+        return
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    nbytes = buf.numel() * buf.element_size()
+    _check("zsort_set_workspace", lib().zsort_set_workspace(
+        ctypes.c_void_p(buf.data_ptr()), nbytes, _stream(stream)))
+
+
+def zsort_set_alloc_limit(max_bytes: int):
+    """Every device allocation above max_bytes fails as out of memory (0: no limit)."""
+    _check("zsort_set_alloc_limit", lib().zsort_set_alloc_limit(int(max_bytes)))
 
 
 def zsort_get_last_stats(stream=None) -> dict:

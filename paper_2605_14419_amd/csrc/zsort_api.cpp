@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -18,6 +19,9 @@
 
 namespace zs {
 hipError_t launch_reset(const Ws& ws, hipStream_t st);
+hipError_t launch_clear_rows(const Ws& ws, int grid, hipStream_t st);
+hipError_t launch_check_sorted(const uint64_t* keys, uint64_t n, uint32_t* flag, int grid,
+                               hipStream_t st);
 hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st);
 hipError_t launch_init_single(const Ws& ws, uint64_t n, hipStream_t st);
 hipError_t launch_init_segments(const Ws& ws, const int64_t* off, int32_t nseg, uint64_t n,
@@ -84,6 +88,9 @@ struct Layout {
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// smallest caller workspace accepted: the control block
+size_t zs_min_workspace() { return align_up(sizeof(zs::Ctl), 256); }
 
 Layout plan(const Shape& s) {
   Layout L{};
@@ -160,6 +167,8 @@ struct Workspace {
   int device = -1;
   char* base = nullptr;
   size_t bytes = 0;
+  bool user = false;       // base is the caller's memory (zsort_set_workspace): never freed
+  bool rows_dirty = true;  // the scan-row region may hold stale words of another layout
   Shape shape;
   Layout lay{};
   bool laid_out = false;
@@ -258,7 +267,18 @@ int levels_for(const zsort_config& c) {
   return std::min(L, zs::kMaxLevels);
 }
 
-// Finds (or grows) the stream's workspace and lays it out for `s`.
+size_t g_alloc_limit = 0;  // zsort_set_alloc_limit: largest device allocation allowed (0: any)
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  if (g_alloc_limit && bytes > g_alloc_limit) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+// Finds (or grows) the stream's workspace and lays it out for `s`.  Under
+// stream capture a new layout is accepted as long as it fits the memory the
+// workspace already has (nothing is allocated while a stream is captured).
+// A caller's workspace (zsort_set_workspace) is never grown: a shape that
+// does not fit returns ZSORT_ENOMEM.
 int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -273,9 +293,10 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
   const Layout L = plan(s);
   const bool same = w->laid_out && w->shape == s;
   if (!same) {
-    if (capturing(st)) return ZSORT_ECAPTURE;
-    drop_graphs(w);
     if (L.total > w->bytes) {
+      if (w->user) return ZSORT_ENOMEM;
+      if (capturing(st)) return ZSORT_ECAPTURE;
+      drop_graphs(w);   // they name the old buffer
       if (w->base) {
         e = hipFree(w->base);
         if (e != hipSuccess) return hip_fail(e);
@@ -283,26 +304,20 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
         w->bytes = 0;
       }
       void* p = nullptr;
-      e = hipMalloc(&p, L.total);
+      e = dev_alloc(&p, L.total);
       if (e != hipSuccess) return hip_fail(e);
       w->base = (char*)p;
       w->bytes = L.total;
       e = hipMemsetAsync(w->base, 0, sizeof(zs::Ctl), st);
       if (e != hipSuccess) return hip_fail(e);
     }
-    // fresh scan rows: no stale word may carry a live tag
-    e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
-    if (e != hipSuccess) return hip_fail(e);
+    // (graphs of other shapes stay valid: a shape's layout in a given buffer
+    // is always the same)
+    w->rows_dirty = true;   // the row region now covers memory of the old layout
     w->device = dev;
     w->shape = s;
     w->lay = L;
     w->laid_out = true;
-    w->calls = 0;
-  } else if (w->calls && (w->calls % 65536u) == 0) {
-    // tags repeat after 2^16 calls: clear the rows before they could
-    if (capturing(st)) return ZSORT_ECAPTURE;
-    e = hipMemsetAsync(w->base + L.off_status, 0, L.status_bytes, st);
-    if (e != hipSuccess) return hip_fail(e);
   }
   *out = w;
   return ZSORT_OK;
@@ -340,6 +355,8 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
   ws.tile_cap = L.tile_cap;
   ws.leaf_cap = L.leaf_cap;
   ws.status_cap = L.status_cap;
+  ws.status_words = L.status_bytes / 8;
+  ws.force_clear = 0;
   ws.p.k = c.k;
   ws.p.lb = floor_log2(c.k);
   ws.p.cutoff = c.cutoff;
@@ -403,6 +420,20 @@ bool pacing_ready(Workspace* w) {
 
 hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st);
 
+// Scan rows of a new layout are cleared before the call's kernels: at once
+// on the stream, or -- while the stream is being captured -- by the set-up
+// kernel of every replay of the caller's graph (k_reset is told to).
+hipError_t prepare_rows(Workspace* w, Ws* ws, hipStream_t st) {
+  if (!w->rows_dirty) return hipSuccess;
+  if (capturing(st)) {
+    ws->force_clear = 1;
+    return hipSuccess;
+  }
+  hipError_t e = zs::launch_clear_rows(*ws, std::max(1, g_cu_count) * 4, st);
+  if (e == hipSuccess) w->rows_dirty = false;
+  return e;
+}
+
 int run(const Call& c, hipStream_t st, Workspace** wout) {
   Shape s;
   s.n = c.n;
@@ -418,8 +449,9 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   Workspace* w = nullptr;
   int rc = acquire(st, s, &w, c.slot);
   if (rc) return rc;
-  const Ws ws = make_ws(w, c.keys, c.pay, c.cfg, c.pw);
-  hipError_t e = hipSuccess;
+  Ws ws = make_ws(w, c.keys, c.pay, c.cfg, c.pw);
+  hipError_t e = prepare_rows(w, &ws, st);
+  if (e != hipSuccess) return hip_fail(e);
   const bool graph = (c.cfg.flags & ZSORT_FLAG_GRAPH) && !c.level0_only && !c.trace_cap &&
                      !capturing(st);
   if (graph) {
@@ -655,7 +687,7 @@ int lacquire(hipStream_t st, uint64_t n, uint64_t m, size_t part_floats, Learned
     if (e != hipSuccess) return hip_fail(e);
   }
   void* p = nullptr;
-  e = hipMalloc(&p, total);
+  e = dev_alloc(&p, total);
   if (e != hipSuccess) return hip_fail(e);
   char* b = (char*)p;
   w->base = b;
@@ -765,18 +797,58 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
 
 size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
                              const zsort_config* cfg) {
-  zsort_config c;
-  if (resolve_cfg(cfg, &c)) return 0;
   if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return 0;
   if (num_segments < 0 || n > 0x7FFFFFFFull) return 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  zsort_config c;
+  // cfg NULL: the configuration such a call would use (tuned entry or defaults)
+  if (resolve_cfg(cfg, &c, n, payload_bytes, num_segments > 0 ? 1 : 0)) return 0;
   Shape s;
   s.n = n;
   s.pw = payload_bytes;
   s.k = c.k;
   s.cutoff = c.cutoff;
   s.chunk = c.chunk;
-  s.nseg = num_segments;
+  s.tile = c.tile;
+  s.nseg = num_segments > 0 ? num_segments : 0;
   return plan(s).total;
+}
+
+int zsort_set_workspace(void* d_ws, size_t bytes, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (d_ws && (((uintptr_t)d_ws & 255u) != 0 || bytes < zs_min_workspace())) return ZSORT_EINVAL;
+  if (!d_ws && bytes) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (capturing(st)) return ZSORT_ECAPTURE;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  Workspace*& w = g_ws[st];
+  if (!w) w = new Workspace();
+  if (w->device != -1 && w->device != dev && w->base) return ZSORT_EINVAL;
+  drop_graphs(w);
+  if (w->base && !w->user) {
+    e = hipFree(w->base);   // the library's own buffer (synchronises the device)
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  w->base = (char*)d_ws;
+  w->bytes = d_ws ? bytes : 0;
+  w->user = d_ws != nullptr;
+  w->laid_out = false;
+  w->rows_dirty = true;
+  w->has_last = false;
+  w->device = dev;
+  if (d_ws) {
+    e = hipMemsetAsync(d_ws, 0, sizeof(zs::Ctl), st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ZSORT_OK;
+}
+
+int zsort_set_alloc_limit(size_t max_bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_alloc_limit = max_bytes;
+  return ZSORT_OK;
 }
 
 int zsort_get_last_stats(void* stream, zsort_stats* out) {
@@ -902,9 +974,11 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
   if (capturing(st)) return ZSORT_ECAPTURE;
   uint64_t* tk = nullptr;
   void* tp = nullptr;
+  uint32_t* flag = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipMalloc(&tk, n * 8);
-  if (e == hipSuccess && payload_bytes) e = hipMalloc(&tp, n * (size_t)payload_bytes);
+  hipError_t e = dev_alloc((void**)&tk, n * 8);
+  if (e == hipSuccess && payload_bytes) e = dev_alloc(&tp, n * (size_t)payload_bytes);
+  if (e == hipSuccess) e = dev_alloc((void**)&flag, 256);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   zsort_config win;
@@ -934,12 +1008,21 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
           if (e != hipSuccess) break;
           Call call{tk, payload_bytes ? tp : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
                     num_segments, c, 0, 0, false};
-          rc = run(call, st, nullptr);
+          Workspace* w = nullptr;
+          rc = run(call, st, &w);
           if (rc) break;
           e = hipEventRecord(e1, st);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          uint32_t derr = 0;   // a device-side limit: the candidate is out
+          if (e == hipSuccess)
+            e = hipMemcpy(&derr, w->base + w->lay.off_ctl + offsetof(zs::Ctl, error), 4,
+                          hipMemcpyDeviceToHost);
+          if (derr) {
+            t_best = 1e30f;
+            break;
+          }
           if (rep > 0 && ms < t_best) t_best = ms;  // first run warms up
         }
         if (rc) break;
@@ -948,12 +1031,32 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
           win = c;
         }
       }
+  // the winner once more: its output must be sorted (single arrays) before it
+  // is remembered
+  uint32_t unsorted = win_ms < 1e29f ? 0u : 1u;
+  if (!rc && e == hipSuccess && !unsorted && !seg_offsets) {
+    e = hipMemcpyAsync(tk, keys, n * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && payload_bytes)
+      e = hipMemcpyAsync(tp, payload, n * (size_t)payload_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4, st);
+    if (e == hipSuccess) {
+      Call call{tk, payload_bytes ? tp : nullptr, payload_bytes, (uint64_t)n, nullptr, 0, win, 0, 0,
+                false};
+      rc = run(call, st, nullptr);
+    }
+    if (!rc && e == hipSuccess)
+      e = zs::launch_check_sorted(tk, n, flag, std::max(1, g_cu_count) * 4, st);
+    if (!rc && e == hipSuccess) e = hipMemcpyAsync(&unsorted, flag, 4, hipMemcpyDeviceToHost, st);
+    if (!rc && e == hipSuccess) e = hipStreamSynchronize(st);
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (tk) (void)hipFree(tk);
   if (tp) (void)hipFree(tp);
+  if (flag) (void)hipFree(flag);
   if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e);
+  if (unsorted) return ZSORT_EDEVICE;   // no candidate ran within its limits
   g_tuned[key] = win;
   if (cache_path) tune_file_write(cache_path);
   if (best) *best = win;
@@ -1004,7 +1107,7 @@ int zsort_release(void) {
   auto free_ws = [&](Workspace* w) {
     drop_graphs(w);
     if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
-    if (w->base) {
+    if (w->base && !w->user) {   // a caller's workspace is the caller's to free
       hipError_t e = hipFree(w->base);
       if (e != hipSuccess) rc = hip_fail(e);
     }
@@ -1149,7 +1252,9 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   rc = acquire(st, s, &w);
   if (rc) return rc;
   if (!pacing_ready(w)) return ZSORT_EHIP;
-  const Ws ws = make_ws(w, keys, pay, c, payload_bytes);
+  Ws ws = make_ws(w, keys, pay, c, payload_bytes);
+  e = prepare_rows(w, &ws, st);
+  if (e != hipSuccess) return hip_fail(e);
   Ws w0 = first_pass_ws(ws, lw, B0, direct);
   w0.lm.sub = (uint32_t)B1;
   const Ws w1 = first_pass_ws(ws, lw, two ? B1 : B0, false);

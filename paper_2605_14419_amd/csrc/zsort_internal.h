@@ -109,6 +109,8 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t tick[kMaxLevels];     // work-item tickets of the hist pass
   uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list
   uint32_t epoch;                // changes every call; tags the scan rows
+  uint32_t clear_epoch;          // epoch at which the scan rows were last cleared
+  uint32_t clear_rows;           // 1: this call's set-up kernel clears the scan rows
   uint32_t error;                // nonzero: a capacity or wait limit was hit
   uint32_t ntrace;
   uint32_t ntrace_hist;
@@ -224,8 +226,18 @@ struct Ws {
   uint32_t* h_nseg;      // pinned host words, or null: the last kernel of level L stores
                          // there the segment count of level L + 1 (0 after an error)
   uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
+  uint32_t force_clear;  // 1: clear the scan rows in this call (set-up of a new layout)
+  uint64_t status_words; // words of the scan-row region
   Params p;
   LMap lm;
 };
+
+// Scan-row tags: within any run of kClearEvery consecutive epochs the tags
+// of (epoch, level) pairs are distinct and never 0 (the value of a cleared
+// word), so a word carries the current tag only if this level of this call
+// wrote it.  The rows are cleared at least once per kClearEvery epochs.
+constexpr uint32_t kTagMod = (1u << 22) - 1u;
+constexpr uint32_t kClearEvery = 60000u;   // * 64 levels < kTagMod
+static_assert((uint64_t)kClearEvery * 64u < kTagMod, "tags must not repeat between clears");
 
 }  // namespace zs

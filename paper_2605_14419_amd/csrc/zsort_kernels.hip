@@ -464,7 +464,7 @@ constexpr uint64_t kValMask = (1ull << 40) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;
 
 __device__ __forceinline__ uint32_t level_tag(uint32_t epoch, int L) {
-  return (epoch * 64u + (uint32_t)L) & 0x3FFFFFu;
+  return 1u + (uint32_t)(((uint64_t)epoch * 64u + (uint32_t)L) % kTagMod);
 }
 __device__ __forceinline__ void row_put(uint64_t* p, uint32_t tag, uint64_t v) {
   __hip_atomic_store(p, ((uint64_t)tag << 42) | (v & kValMask), __ATOMIC_RELAXED,
@@ -516,7 +516,15 @@ __global__ void k_reset(Ws ws) {
     c->lvl_segs[t] = 0;
   }
   if (t == 0) {
-    c->epoch = c->epoch + 1u;
+    const uint32_t ep = c->epoch + 1u;
+    c->epoch = ep;
+    // a new layout of the rows, the end of the window in which tags are
+    // distinct, or the wrap of the epoch counter (tags before and after it
+    // are not distinct): the set-up kernel of this call clears the rows
+    const bool clr = ws.force_clear != 0u || ep == 0u ||
+                     (uint32_t)(ep - c->clear_epoch) >= kClearEvery;
+    c->clear_rows = clr ? 1u : 0u;
+    if (clr) c->clear_epoch = ep;
     for (int s = 0; s < 2; ++s) {
       c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nleafm[s] = 0; c->nhard[s] = 0;
       c->nstatus[s] = 0; c->ntile[s] = 0;
@@ -595,8 +603,29 @@ __device__ void init_root_arrivals(Ws& ws, uint32_t nch) {
     ws.arrive[0][i] = 0u;
 }
 
+// the scan rows, zeroed by the whole grid when k_reset asked for it (no row
+// is read before the histogram pass, which runs after this kernel)
+__device__ void clear_rows_if_due(const Ws& ws) {
+  if (__hip_atomic_load(&ws.ctl->clear_rows, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+    return;
+  const uint64_t np = ws.status_words >> 1;
+  ulonglong2* p = reinterpret_cast<ulonglong2*>(ws.status);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride)
+    p[i] = make_ulonglong2(0ull, 0ull);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (ws.status_words & 1u))
+    ws.status[ws.status_words - 1] = 0ull;
+}
+
+__global__ void k_clear_rows(Ws ws) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.status_words; i += stride)
+    ws.status[i] = 0ull;
+}
+
 // one array [0, n): root segment (n > cutoff) or a single leaf
 __global__ void k_init_single(Ws ws, uint64_t n) {
+  clear_rows_if_due(ws);
   Ctl* c = ws.ctl;
   const uint64_t ch = (uint64_t)ws.p.chunk;
   if (n <= (uint64_t)ws.p.cutoff) {
@@ -630,6 +659,7 @@ __global__ void k_reset_lists(Ws ws, int slot) {
 
 // one array [0, n), n > cutoff, whose first pass uses the learned map
 __global__ void k_init_learned(Ws ws, uint64_t n) {
+  clear_rows_if_due(ws);
   Ctl* c = ws.ctl;
   const uint64_t ch = (uint64_t)ws.p.chunk;
   const uint32_t nch = (uint32_t)((n + ch - 1) / ch);
@@ -657,6 +687,7 @@ __global__ void k_init_learned(Ws ws, uint64_t n) {
 
 // independent arrays [off[i], off[i+1]); offsets were validated by k_check_offsets
 __global__ void k_check_offsets(Ws ws, const int64_t* off, int32_t nseg, uint64_t n) {
+  clear_rows_if_due(ws);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= nseg; i += gridDim.x * blockDim.x) {
     bool bad = false;
     if (i == 0 && off[0] != 0) bad = true;
@@ -2546,6 +2577,26 @@ hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st) {
 
 hipError_t launch_reset(const Ws& ws, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, ws);
+  return hipGetLastError();
+}
+
+// *flag = 1 if some keys[i] > keys[i + 1]
+__global__ void k_check_sorted(const uint64_t* __restrict__ x, uint64_t n, uint32_t* flag) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += stride)
+    bad |= x[i] > x[i + 1];
+  if (__any(bad) && lane() == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_check_sorted(const uint64_t* keys, uint64_t n, uint32_t* flag, int grid,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_check_sorted, dim3(grid), dim3(kBlock), 0, st, keys, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_rows(const Ws& ws, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_rows, dim3(grid), dim3(kBlock), 0, st, ws);
   return hipGetLastError();
 }
 

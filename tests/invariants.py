@@ -32,3 +32,64 @@ def stable_reference(keys, payload=None):
     k = np.asarray(keys, dtype=np.uint64)[order]
     p = None if payload is None else np.asarray(payload)[order]
     return k, p
+
+
+# ---------------------------------------------------------------------------
+# The same three properties checked on the device (torch ops on CUDA tensors),
+# for arrays too large to copy to the host and check there: keys are u64 bits
+# in int64 tensors, ordered as unsigned numbers; the payload is the index of
+# each key (u32 bits in an int32 tensor, or int64).
+# ---------------------------------------------------------------------------
+def _unsigned_order(k):
+    import torch
+    return k ^ torch.tensor(-(2**63), dtype=torch.int64, device=k.device)
+
+
+def _as_index(p):
+    import torch
+    return p.long() & 0xFFFFFFFF if p.dtype == torch.int32 else p.long()
+
+
+def check_stable_sorted_device(k_in, k_out, idx_out):
+    """Sorted, a permutation whose index carries its key, stable (device)."""
+    import torch
+    ks = _unsigned_order(k_out)
+    n = k_out.numel()
+    assert k_in.numel() == n, "size changed"
+    if n == 0:
+        return
+    assert bool((ks[1:] >= ks[:-1]).all()), "keys not non-decreasing"
+    if idx_out is None:
+        return
+    idx = _as_index(idx_out)
+    assert int(idx.min()) >= 0 and int(idx.max()) < n, "index out of range"
+    seen = torch.zeros(n, dtype=torch.int8, device=k_out.device)
+    seen.index_fill_(0, idx, 1)
+    assert int(seen.sum(dtype=torch.int64)) == n, "index payload is not a permutation"
+    assert bool((k_in[idx] == k_out).all()), "key does not match its index"
+    eq = ks[1:] == ks[:-1]
+    assert bool((idx[1:][eq] > idx[:-1][eq]).all()), "equal keys out of input order"
+
+
+def check_segmented_stable_sorted_device(k_in, k_out, idx_out, offsets):
+    """The three properties inside every segment [off[i], off[i+1]): the
+    payload is each key's index within its own segment."""
+    import torch
+    dev = k_out.device
+    n = k_out.numel()
+    off = offsets.to(dev).long()
+    lens = off[1:] - off[:-1]
+    assert int(off[0]) == 0 and int(off[-1]) == n and bool((lens >= 0).all()), "bad offsets"
+    sid = torch.repeat_interleave(torch.arange(lens.numel(), device=dev), lens)
+    ks = _unsigned_order(k_out)
+    same = sid[1:] == sid[:-1]
+    assert bool(((ks[1:] >= ks[:-1]) | ~same).all()), "keys not non-decreasing in a segment"
+    loc = _as_index(idx_out)
+    assert bool((loc < lens[sid]).all()) and int(loc.min()) >= 0, "index outside its segment"
+    gidx = off[:-1][sid] + loc
+    seen = torch.zeros(n, dtype=torch.int8, device=dev)
+    seen.index_fill_(0, gidx, 1)
+    assert int(seen.sum(dtype=torch.int64)) == n, "index payload is not a permutation"
+    assert bool((k_in[gidx] == k_out).all()), "key does not match its index"
+    eq = (ks[1:] == ks[:-1]) & same
+    assert bool((loc[1:][eq] > loc[:-1][eq]).all()), "equal keys out of input order"

@@ -90,3 +90,41 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(zs, "_lib", None)
     with pytest.raises(RuntimeError):
         zs.lib()
+
+
+def test_workspace_bytes_follows_tile_and_set_workspace_checks_arguments():
+    # 8192-key tiles need per-tile prefix rows and tile lists: more bytes
+    n = 10**7
+    b2 = zs.zsort_workspace_bytes(n, 4, 0, dict(k=512, chunk=32768, tile=2048))
+    b8 = zs.zsort_workspace_bytes(n, 4, 0, dict(k=512, chunk=32768, tile=8192))
+    assert b8 > b2 > 0
+    L = zs.lib()
+    # misaligned, too small, or NULL with a size: rejected before any HIP call
+    assert L.zsort_set_workspace(ctypes.c_void_p(4096 + 8), 1 << 20, None) == zs.ZSORT_EINVAL
+    assert L.zsort_set_workspace(ctypes.c_void_p(4096), 64, None) == zs.ZSORT_EINVAL
+    assert L.zsort_set_workspace(None, 1 << 20, None) == zs.ZSORT_EINVAL
+    assert L.zsort_set_alloc_limit(0) == zs.ZSORT_OK
+
+
+def test_scan_row_tags_are_distinct_and_nonzero_between_clears():
+    """The histogram pass's scan-row words carry tag(epoch, level) =
+    1 + (64 epoch + level) mod kTagMod; rows are cleared (tag 0) at least once
+    every kClearEvery epochs.  Between two clears every (epoch, level) pair
+    must have its own tag, never 0, at any epoch offset, including across the
+    32-bit wrap of the epoch counter."""
+    import re
+    import numpy as np
+    src = open(os.path.join(ROOT, "paper_2605_14419_amd", "csrc", "zsort_internal.h")).read()
+    mod = eval(re.search(r"kTagMod\s*=\s*([^;]+);", src).group(1).replace("u", ""))
+    every = int(re.search(r"kClearEvery\s*=\s*(\d+)u", src).group(1))
+    kern = open(os.path.join(ROOT, "paper_2605_14419_amd", "csrc", "zsort_kernels.hip")).read()
+    assert "return 1u + (uint32_t)(((uint64_t)epoch * 64u + (uint32_t)L) % kTagMod);" in kern
+    # the epoch counter's wrap to 0 forces a clear as well
+    assert "ep == 0u ||" in kern
+    levels = 40
+    for e0 in [0, 1, 12345, 2**22, 2**32 - every]:
+        ep = (np.arange(e0, e0 + every, dtype=np.uint64) % np.uint64(2**32))
+        t = 1 + (ep[:, None] * np.uint64(64) + np.arange(levels, dtype=np.uint64)[None, :]) % np.uint64(mod)
+        t = t.reshape(-1)
+        assert t.min() >= 1 and t.max() < 2**22
+        assert np.unique(t).size == t.size, e0

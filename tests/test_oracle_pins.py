@@ -376,3 +376,41 @@ def test_invariant_checker_rejects_errors():
         check_stable_sorted(x, np.array([1, 3, 5, 4], dtype=np.uint64), good_i)
     with pytest.raises(AssertionError):
         check_stable_sorted(x, good_k, np.array([3, 1, 0, 0]))       # not a permutation
+
+
+def test_device_checkers_reject_planted_mistakes_on_cpu_tensors():
+    """The torch forms of the three properties (used at 10^8 keys on the
+    device) accept a correct stable sort and reject each planted mistake."""
+    torch = pytest.importorskip("torch")
+    from tests.invariants import (check_segmented_stable_sorted_device,
+                                  check_stable_sorted_device)
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 6, size=400).astype(np.uint64) * np.uint64(2**62 // 3)
+    order = np.argsort(x, kind="stable")
+    kin = torch.from_numpy(x.view(np.int64))
+    kout = torch.from_numpy(x[order].view(np.int64))
+    iout = torch.from_numpy(order.astype(np.int32))
+    check_stable_sorted_device(kin, kout, iout)
+    bad_unstable = iout.clone()
+    eqpos = np.nonzero(x[order][1:] == x[order][:-1])[0][0]
+    bad_unstable[eqpos], bad_unstable[eqpos + 1] = iout[eqpos + 1], iout[eqpos]
+    bad_keys = kout.clone()
+    bad_keys[0], bad_keys[-1] = kout[-1], kout[0]
+    bad_perm = iout.clone()
+    bad_perm[3] = bad_perm[4]
+    for k, i, what in [(kout, bad_unstable, "order"), (bad_keys, iout, "non-decreasing"),
+                       (kout, bad_perm, "permutation")]:
+        with pytest.raises(AssertionError, match=what):
+            check_stable_sorted_device(kin, k, i)
+    # segmented: two segments, each sorted on its own
+    off = torch.tensor([0, 150, 400])
+    parts_k, parts_i = [], []
+    for a, b in [(0, 150), (150, 400)]:
+        o = np.argsort(x[a:b], kind="stable")
+        parts_k.append(x[a:b][o])
+        parts_i.append(o.astype(np.int32))
+    sk = torch.from_numpy(np.concatenate(parts_k).view(np.int64))
+    si = torch.from_numpy(np.concatenate(parts_i))
+    check_segmented_stable_sorted_device(kin, sk, si, off)
+    with pytest.raises(AssertionError):   # sorted as one array is not per segment
+        check_segmented_stable_sorted_device(kin, kout, iout, off)
