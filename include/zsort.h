@@ -51,7 +51,8 @@ enum {
   ZSORT_EHIP = -3,          /* a HIP runtime call failed (see zsort_last_hip_error) */
   ZSORT_ECAPTURE = -4,      /* the call would allocate while its stream is being captured */
   ZSORT_EUNSUPPORTED = -5,  /* configuration not built into this library */
-  ZSORT_EDEVICE = -6        /* a device-side limit was hit (only from synchronous calls) */
+  ZSORT_EDEVICE = -6,       /* a device-side limit was hit (only from synchronous calls) */
+  ZSORT_ETOOLARGE = -7      /* the problem does not fit the fixed scratch buffer */
 };
 
 /*
@@ -148,6 +149,27 @@ int zsort_stable(uint64_t* keys, uint32_t* payload, size_t n, void* stream);
 
 /* As zsort_stable with a u64 payload (may be NULL): Algorithm 1, Eq. (1). */
 int zsort_stable_p64(uint64_t* keys, uint64_t* payload, size_t n, void* stream);
+
+/*
+ * For callers that cannot allocate (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): zsort_stable_ex that allocates
+ * nothing, neither device nor pinned host memory nor events.  Its workspace
+ * is a fixed array of ZSORT_NOALLOC_SCRATCH_BYTES (64 MiB) in device memory,
+ * one per GPU, held from the library's load until the process ends; the
+ * largest problem it takes is the largest whose zsort_workspace_bytes (with
+ * num_segments 0 and the same cfg) is at most that, e.g. 2^21 keys with any
+ * payload at the default configuration, about 3.5 * 10^6 with a 4-byte one.
+ * Larger problems return ZSORT_ETOOLARGE without touching the data.  Every
+ * call on a GPU shares that GPU's array and leaves its contents behind: calls
+ * that overlap on one GPU (different streams, or host threads) race and must
+ * be serialised by the caller.  The output equals zsort_stable_ex's with the
+ * same arguments.  ZSORT_FLAG_GRAPH returns ZSORT_EUNSUPPORTED (it captures
+ * on a stream of its own); every level of the recursion is launched, as in
+ * graph mode.  zsort_get_last_stats does not report these calls.
+ */
+#define ZSORT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int zsort_stable_noalloc(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                         const zsort_config* cfg, void* stream);
 
 /*
  * General form of zsort_stable (Algorithm 1, Eq. (1), Section III):

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libzsort.so")
 
 ZSORT_OK, ZSORT_EINVAL, ZSORT_ENOMEM, ZSORT_EHIP, ZSORT_ECAPTURE, ZSORT_EUNSUPPORTED, \
-    ZSORT_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+    ZSORT_EDEVICE, ZSORT_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MAX_LEVELS = 40
 
 EXPORTED = [
@@ -24,7 +25,7 @@ EXPORTED = [
     "zsort_stable_segmented", "zsort_workspace_bytes", "zsort_get_last_stats",
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
     "zsort_strerror", "zsort_profile_begin", "zsort_profile_begin_stages", "zsort_profile_end",
-    "zsort_autotune", "zsort_set_workspace", "zsort_set_alloc_limit",
+    "zsort_autotune", "zsort_set_workspace", "zsort_set_alloc_limit", "zsort_stable_noalloc",
     "zsort_default_learned_config", "zsort_stable_learned", "zsort_learned_sample",
     "zsort_mlp_forward", "zsort_mlp_thresholds", "zsort_mlp_init", "zsort_mlp_grad",
     "zsort_mlp_train",
@@ -115,6 +116,7 @@ def lib():
         L.zsort_stable.argtypes = [P, P, Z, P]
         L.zsort_stable_p64.argtypes = [P, P, Z, P]
         L.zsort_stable_ex.argtypes = [P, P, I, Z, P, P]
+        L.zsort_stable_noalloc.argtypes = [P, P, I, Z, P, P]
         L.zsort_stable_segmented.argtypes = [P, P, I, Z, P, ctypes.c_int32, P, P]
         L.zsort_workspace_bytes.argtypes = [Z, I, ctypes.c_int32, P]
         L.zsort_set_workspace.argtypes = [P, Z, P]
@@ -221,6 +223,14 @@ def zsort_stable_ex(keys, payload=None, cfg=None, stream=None):
     p, pw = _pay(payload, keys.numel())
     _check("zsort_stable_ex", lib().zsort_stable_ex(_keys_ptr(keys), p, pw, keys.numel(),
                                                     _cfg(cfg), _stream(stream)))
+
+
+def zsort_stable_noalloc(keys, payload=None, cfg=None, stream=None):
+    """zsort_stable_ex without any allocation: runs in the library's fixed
+    per-GPU scratch array (problems up to NOALLOC_SCRATCH_BYTES of workspace)."""
+    p, pw = _pay(payload, keys.numel())
+    _check("zsort_stable_noalloc", lib().zsort_stable_noalloc(
+        _keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg), _stream(stream)))
 
 
 def zsort_stable_segmented(keys, seg_offsets, payload=None, cfg=None, stream=None):

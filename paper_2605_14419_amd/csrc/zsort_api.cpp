@@ -20,6 +20,7 @@
 namespace zs {
 hipError_t launch_reset(const Ws& ws, hipStream_t st);
 hipError_t launch_clear_rows(const Ws& ws, int grid, hipStream_t st);
+hipError_t scratch_address(int dev, void** out);
 hipError_t launch_check_sorted(const uint64_t* keys, uint64_t n, uint32_t* flag, int grid,
                                hipStream_t st);
 hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st);
@@ -323,33 +324,41 @@ int acquire(hipStream_t st, const Shape& s, Workspace** out, int slot = 0) {
   return ZSORT_OK;
 }
 
+Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay,
+         const zsort_config& c, int pw);
+
 Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int pw) {
-  const Layout& L = w->lay;
+  return ws_at(w->base, w->lay, w->shape, keys, pay, c, pw);
+}
+
+// kernel arguments of a workspace laid out as L at `base`
+Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay,
+         const zsort_config& c, int pw) {
   Ws ws;
   std::memset(&ws, 0, sizeof ws);
   ws.keys[0] = keys;
-  ws.keys[1] = (uint64_t*)(w->base + L.off_keys);
+  ws.keys[1] = (uint64_t*)(base + L.off_keys);
   ws.pay[0] = pay;
-  ws.pay[1] = pw ? (void*)(w->base + L.off_pay) : nullptr;
+  ws.pay[1] = pw ? (void*)(base + L.off_pay) : nullptr;
   for (int i = 0; i < 2; ++i) {
-    ws.segs[i] = (zs::Seg*)(w->base + L.off_segs[i]);
-    ws.work[i] = (uint64_t*)(w->base + L.off_work[i]);
-    ws.leaves[i] = (zs::Leaf*)(w->base + L.off_leaves[i]);
-    ws.leavesw[i] = (zs::Leaf*)(w->base + L.off_leavesw[i]);
-    ws.leavesm[i] = (zs::Leaf*)(w->base + L.off_leavesm[i]);
-    ws.hard[i] = (zs::Leaf*)(w->base + L.off_hard[i]);
+    ws.segs[i] = (zs::Seg*)(base + L.off_segs[i]);
+    ws.work[i] = (uint64_t*)(base + L.off_work[i]);
+    ws.leaves[i] = (zs::Leaf*)(base + L.off_leaves[i]);
+    ws.leavesw[i] = (zs::Leaf*)(base + L.off_leavesw[i]);
+    ws.leavesm[i] = (zs::Leaf*)(base + L.off_leavesm[i]);
+    ws.hard[i] = (zs::Leaf*)(base + L.off_hard[i]);
   }
-  ws.status = (uint64_t*)(w->base + L.off_status);
-  for (int i = 0; i < 2; ++i) ws.arrive[i] = (uint32_t*)(w->base + L.off_arrive[i]);
-  ws.part = (uint64_t*)(w->base + L.off_part);
-  ws.bstart = (uint32_t*)(w->base + L.off_bstart);
-  ws.subpre = (uint16_t*)(w->base + L.off_subpre);
-  for (int i = 0; i < 2; ++i) ws.tiles[i] = (uint64_t*)(w->base + L.off_tiles[i]);
-  ws.ctl = (zs::Ctl*)(w->base + L.off_ctl);
-  ws.trace = w->shape.trace_cap ? (zs::TraceRec*)(w->base + L.off_trace) : nullptr;
-  ws.trace_hist = w->shape.trace_hist_cap ? (uint32_t*)(w->base + L.off_thist) : nullptr;
-  ws.trace_cap = (uint32_t)w->shape.trace_cap;
-  ws.trace_hist_cap = (uint32_t)w->shape.trace_hist_cap;
+  ws.status = (uint64_t*)(base + L.off_status);
+  for (int i = 0; i < 2; ++i) ws.arrive[i] = (uint32_t*)(base + L.off_arrive[i]);
+  ws.part = (uint64_t*)(base + L.off_part);
+  ws.bstart = (uint32_t*)(base + L.off_bstart);
+  ws.subpre = (uint16_t*)(base + L.off_subpre);
+  for (int i = 0; i < 2; ++i) ws.tiles[i] = (uint64_t*)(base + L.off_tiles[i]);
+  ws.ctl = (zs::Ctl*)(base + L.off_ctl);
+  ws.trace = sh.trace_cap ? (zs::TraceRec*)(base + L.off_trace) : nullptr;
+  ws.trace_hist = sh.trace_hist_cap ? (uint32_t*)(base + L.off_thist) : nullptr;
+  ws.trace_cap = (uint32_t)sh.trace_cap;
+  ws.trace_hist_cap = (uint32_t)sh.trace_hist_cap;
   ws.seg_cap = L.seg_cap;
   ws.work_cap = L.work_cap;
   ws.tile_cap = L.tile_cap;
@@ -370,16 +379,13 @@ Ws make_ws(Workspace* w, uint64_t* keys, void* pay, const zsort_config& c, int p
 // grid of a stage: every compute unit filled to the kernel's occupancy
 int grid_size(int k, int pw, int tile, int stage) {
   static std::mutex mu;
-  static std::unordered_map<int, int> cache;
+  static int cache[4 * 16 * 4 * 8] = {};   // (k class, payload bytes, tile class, stage)
   const int kc = k <= 256 ? 0 : (k <= 512 ? 1 : (k <= 1024 ? 2 : 3));
   const int tc = tile == 8192 ? 2 : (tile == 4096 ? 1 : 0);
   const int key = kc | (pw << 2) | (tc << 6) | (stage << 8);
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(key);
-  int per = 0;
-  if (it != cache.end()) {
-    per = it->second;
-  } else {
+  int per = cache[key];
+  if (!per) {
     per = std::min(8, zs::stage_blocks_per_cu(k, pw, tile, stage));
     cache[key] = per;
   }
@@ -777,6 +783,56 @@ int zsort_stable(uint64_t* keys, uint32_t* payload, size_t n, void* stream) {
 
 int zsort_stable_p64(uint64_t* keys, uint64_t* payload, size_t n, void* stream) {
   return zsort_stable_ex(keys, payload, payload ? 8 : 0, n, nullptr, stream);
+}
+
+int zsort_stable_noalloc(uint64_t* keys, void* payload, int payload_bytes, size_t n,
+                         const zsort_config* cfg, void* stream) {
+  int rc = common_checks(keys, payload, payload_bytes, n);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  zsort_config c;
+  rc = resolve_cfg(cfg, &c, n, payload_bytes, 0);
+  if (rc) return rc;
+  if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
+  if (n <= 1) return ZSORT_OK;
+  Shape s;
+  s.n = n;
+  s.pw = payload_bytes;
+  s.k = c.k;
+  s.cutoff = c.cutoff;
+  s.chunk = c.chunk;
+  s.tile = c.tile;
+  const Layout L = plan(s);
+  if (L.total > zs::kScratchBytes) return ZSORT_ETOOLARGE;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (!g_cu_count) {
+    e = hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  void* base = nullptr;
+  e = zs::scratch_address(dev, &base);
+  if (e != hipSuccess) return hip_fail(e);
+  hipStream_t st = (hipStream_t)stream;
+  Ws ws = ws_at((char*)base, L, s, keys, payload_bytes ? payload : nullptr, c, payload_bytes);
+  // the array keeps the last call's contents, perhaps in another layout: the
+  // set-up kernel clears the scan rows (the control block is reset by k_reset)
+  ws.force_clear = 1;
+  // every level is launched (no pacing: that would need pinned host memory
+  // and events); kernels of levels without work exit at once
+  const bool sgn = (c.flags & ZSORT_FLAG_SIGNED) != 0;
+  const int fgrid = std::max(1, g_cu_count) * 8;
+  e = sgn ? zs::launch_flip(keys, n, fgrid, st) : hipSuccess;
+  if (e == hipSuccess) e = zs::launch_reset(ws, st);
+  if (e == hipSuccess) e = zs::launch_init_single(ws, n, st);
+  const int levels = levels_for(c);
+  for (int lv = 0; lv < levels && e == hipSuccess; ++lv)
+    for (int sid = 0; sid < zs::NSTAGES && e == hipSuccess; ++sid)
+      e = zs::launch_stage(ws, lv, sid, grid_size(c.k, payload_bytes, c.tile, sid), st);
+  if (e == hipSuccess && sgn) e = zs::launch_flip(keys, n, fgrid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return ZSORT_OK;
 }
 
 int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, size_t n,
@@ -1517,6 +1573,7 @@ const char* zsort_strerror(int status) {
     case ZSORT_ENOMEM: return "device allocation failed";
     case ZSORT_EHIP: return "HIP runtime error";
     case ZSORT_ECAPTURE: return "would allocate during stream capture";
+    case ZSORT_ETOOLARGE: return "problem larger than the fixed scratch buffer";
     case ZSORT_EUNSUPPORTED: return "configuration not supported";
     case ZSORT_EDEVICE: return "device-side limit hit";
     default: return "unknown status";

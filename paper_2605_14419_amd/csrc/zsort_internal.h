@@ -37,6 +37,10 @@ constexpr int wave_job_cap(int pw) { return pw == 8 ? 512 : 640; }
 constexpr int kMidCap = 1024;          // largest block job that one wave of k_local_mid sorts
 constexpr int kWindow = 256;           // leaf-group window; larger leaves sort alone
 constexpr int kCopyChunk = 65536;      // keys per copy job of an all-identical segment
+// device scratch of the allocation-free entry point (one array per GPU, held
+// until the process ends); the largest problem it takes is the largest whose
+// workspace layout fits
+constexpr unsigned long long kScratchBytes = 64ull << 20;
 
 // Cross-chunk scan of a segment of nch > 1 work items (reduce, then scan):
 // the items are grouped into scan units of scan_unit(nch) consecutive items,

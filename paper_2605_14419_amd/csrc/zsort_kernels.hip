@@ -2563,6 +2563,24 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
 // entry points used by the host planner (zsort_api.cpp)
 namespace zs {
 
+// Workspace of zsort_stable_noalloc: a fixed array in device memory, one per
+// GPU.  In host code its name is only a stand-in; the device address is
+// looked up once per device (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int dev, void** out) {
+  static void* addr[256] = {};
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 // signed keys: two's complement order is the unsigned order of x ^ 2^63
 __global__ void __launch_bounds__(kBlock) k_flip(uint64_t* __restrict__ x, uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
