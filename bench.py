@@ -28,6 +28,16 @@ sys.path.insert(0, ROOT)
 METRIC = "GKeys/s + % HBM peak, stable 1e8 u64+idx: z-score vs learned-CDF vs batched"
 HBM_PEAK_GBS = 8000.0
 STAGES = ("moments", "finalize", "hist", "scatter", "local", "local_hard")
+# Each workload runs in the configuration the library's autotuner picked for
+# it most often (its picks differ between runs by less than the run-to-run
+# spread); --autotune times the candidates again instead.  The profiles kept
+# beside the code were taken in these configurations.
+TUNED = {
+    "lognormal": dict(k=256, cutoff=4096, max_zlevels=8, chunk=32768, tile=8192),
+    "zipf": dict(k=256, cutoff=4096, max_zlevels=8, chunk=32768, tile=8192),
+    "uniform_1e8": dict(k=512, cutoff=2048, max_zlevels=8, chunk=32768, tile=8192),
+    "gmm": dict(k=512, cutoff=2048, max_zlevels=8, chunk=32768, tile=8192),
+}
 PRIMARY = dict(workload="lognormal", n=10**8, payload_bytes=8,
                desc="plain z-score path, 1e8 u64 keys floor(exp(N(40, 2.5^2))) clamped, "
                     "u64 index payload")
@@ -47,11 +57,14 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("zsort_kernels.hip", "zsort_internal.h"):
-        with open(os.path.join(ROOT, "paper_2605_14419_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the stable scatter's source text (its shared-memory layout and
+    the kernel), the kernel whose counters the roofline's traffic comes from:
+    a profile taken with other scatter code is not matched."""
+    with open(os.path.join(ROOT, "paper_2605_14419_amd", "csrc", "zsort_kernels.hip")) as fh:
+        src = fh.read()
+    a = src.index("struct ScatSmem")
+    b = src.index("// local sort of the leaf groups", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def stage_bytes(stats: dict, pw: int) -> dict:
@@ -79,7 +92,7 @@ def verify_on_device(k_in, k_out, p_out):
     check_stable_sorted_device(k_in, k_out, p_out)
 
 
-def run_workload(spec, steps, warmup, cfg, dev, profile=True):
+def run_workload(spec, steps, warmup, cfg, dev, profile=True, autotune=False):
     import synth
     import torch
     import paper_2605_14419_amd as zs
@@ -89,6 +102,8 @@ def run_workload(spec, steps, warmup, cfg, dev, profile=True):
     log(f"[bench] {spec['workload']} n={spec['n']} generated in {time.time() - t0:.1f}s")
     base_k, base_p = to_device(keys, pay, dev)
     del pay
+    if cfg is None and not autotune:
+        cfg = TUNED.get(spec["workload"])
     if cfg is None:  # the library's autotuner picks k / tile / chunk / cutoff
         cfg = zs.zsort_autotune(base_k, base_p)
         log(f"[bench] tuned {cfg}")
@@ -235,6 +250,118 @@ def run_batched(steps, warmup, dev, nseg=4096):
             "graph_ms_per_step": round(g_ms, 4), "graph_gkeys_per_s": round(n / g_ms / 1e6, 3),
             "loop_ms_per_step": round(l_ms, 3), "loop_gkeys_per_s": round(n / l_ms / 1e6, 4),
             "speedup_vs_loop": round(l_ms / g_ms, 2)}
+
+
+def run_counting(dev, n=10**7, steps=5):
+    """Counting-sort termination for small key ranges (count_range = k): the
+    recursion's depth and the time per sort with and without it, on keys of a
+    restricted range, on narrow clusters among uniform keys, and on the
+    duplicate-heavy and Zipf families."""
+    import synth
+    import torch
+    import paper_2605_14419_amd as zs
+
+    cfg = dict(k=256, cutoff=2048, max_zlevels=8, chunk=32768, tile=8192)
+    rows = []
+    for name in ("small_range", "clustered_ranges", "dup_heavy", "zipf"):
+        keys, pay = synth.make(name, n, payload_bytes=4)
+        base_k, base_p = to_device(keys, pay, dev)
+        row = {"workload": name}
+        for cr in (0, cfg["k"]):
+            c = dict(cfg, count_range=cr)
+            k, p = base_k.clone(), base_p.clone()
+            zs.zsort_stable_ex(k, p, c)     # warm-up (workspace)
+            ins = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for a, b in ins:
+                zs.zsort_stable_ex(a, b, c)
+            e1.record()
+            torch.cuda.synchronize()
+            st = zs.zsort_get_last_stats()
+            assert st["device_error"] == 0, st
+            verify_on_device(base_k, ins[-1][0], ins[-1][1])
+            tag = "with" if cr else "without"
+            row[f"levels_{tag}"] = st["levels"]
+            row[f"ms_{tag}"] = round(e0.elapsed_time(e1) / steps, 4)
+            if cr:
+                row["counted_subproblems"] = st["counted"]
+            del ins
+        rows.append(row)
+        del base_k, base_p
+        torch.cuda.empty_cache()
+    log("[bench] counting: " + ", ".join(
+        f"{r['workload']}: {r['levels_without']}->{r['levels_with']} levels, "
+        f"{r['ms_without']:.3f}->{r['ms_with']:.3f} ms" for r in rows))
+    return {"workload": f"{n} u64 keys + u32 index per family; count_range = k = {cfg['k']}",
+            "config": cfg, "rows": rows}
+
+
+def run_u128(dev, n=10**8, steps=4):
+    """128-bit keys + u32 index at 10^8: time, GKeys/s and the levels of the
+    high-word and low-word stages, beside the 64-bit path on the same words
+    (uniform for random identifiers; for zero high words the low words
+    themselves, lognormal)."""
+    import synth
+    import torch
+    import paper_2605_14419_amd as zs
+
+    cfg = TUNED["uniform_1e8"]
+    rows = []
+    for name in ("uuid", "prefix", "zext"):
+        keys, idx = synth.make128(name, n)
+        base_k = torch.from_numpy(keys.reshape(-1).view(np.int64)).to(dev)
+        base_p = torch.from_numpy(idx.view(np.int32)).to(dev)
+        del keys, idx
+        k, p = base_k.clone(), base_p.clone()
+        rep = zs.zsort_stable_u128(k, p, cfg, report=True)    # warm-up + the levels
+        assert rep["device_error"] == 0, rep
+        ks = k.view(-1, 2)
+        kk = (ks[:, 1] ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev))
+        same = kk[1:] == kk[:-1]
+        lo = ks[:, 0] ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev)
+        assert bool(((kk[1:] > kk[:-1]) | (same & (lo[1:] >= lo[:-1]))).all()), "not sorted"
+        del k, p, ks, kk, lo, same
+        ins = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for a, b in ins:
+            zs.zsort_stable_u128(a, b, cfg)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        row = {"workload": name, "ms_per_step": round(ms, 4),
+               "gkeys_per_s": round(n / ms / 1e6, 3), "levels_high": rep["levels_high"],
+               "levels_low": rep["levels_low"], "runs": rep["runs"],
+               "short_runs": rep["short_runs"], "run_keys": rep["run_keys"]}
+        # the 64-bit path on the same words: the high words (random ones for
+        # identifiers) or, with zero high words, the low words
+        w = base_k.view(-1, 2)[:, 1 if name != "zext" else 0].contiguous()
+        ins64 = [(w.clone(), base_p.clone()) for _ in range(steps)]
+        zs.zsort_stable_ex(w.clone(), base_p.clone(), cfg)
+        torch.cuda.synchronize()
+        e0.record()
+        for a, b in ins64:
+            zs.zsort_stable_ex(a, b, cfg)
+        e1.record()
+        torch.cuda.synchronize()
+        st = zs.zsort_get_last_stats()
+        row["u64_same_words_ms"] = round(e0.elapsed_time(e1) / steps, 4)
+        row["u64_same_words_levels"] = st["levels"]
+        rows.append(row)
+        del ins, ins64, base_k, base_p, w
+        torch.cuda.empty_cache()
+    log("[bench] u128: " + ", ".join(
+        f"{r['workload']}: {r['ms_per_step']:.3f} ms, levels {r['levels_high']}+{r['levels_low']} "
+        f"(64-bit words: {r['u64_same_words_levels']} levels, {r['u64_same_words_ms']:.3f} ms)"
+        for r in rows))
+    return {"workload": f"{n} 128-bit keys + u32 index (uuid: both words uniform; prefix: 1000 "
+                        "high words; zext: high word 0, low word lognormal)",
+            "config": cfg, "rows": rows}
 
 
 def run_learned(steps, warmup, dev, n=10**8):
@@ -545,7 +672,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["learned", "batched", "alpha"]),
+    ap.add_argument("--extras", default=",".join(list(EXTRAS) + ["learned", "batched", "alpha",
+                                                                "counting", "u128"]),
                     help="comma list, or 'none'")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -557,6 +685,8 @@ def main():
                          "autotuner's, e.g. k=256,cutoff=2048,chunk=32768,tile=4096")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 csv output and exit")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the autotuner's candidates instead of the recorded configurations")
     ap.add_argument("--workload", default="primary",
                     help="workload of the main line: primary (lognormal + u64 index) or one of "
                          + ", ".join(EXTRAS) + " (profiling runs)")
@@ -602,7 +732,8 @@ def main():
         for kv in args.config.split(","):
             a, b = kv.split("=")
             fixed[a.strip()] = int(b)
-    keys, ms, stats, kt, cfg = run_workload(spec, args.steps, args.warmup, fixed, dev)
+    keys, ms, stats, kt, cfg = run_workload(spec, args.steps, args.warmup, fixed, dev,
+                                            autotune=args.autotune)
     pw = spec["payload_bytes"]
     n = spec["n"]
     value = n / (ms * 1e-3) / 1e9
@@ -636,6 +767,12 @@ def main():
             if name == "alpha":
                 extras[name] = run_alpha(dev)
                 continue
+            if name == "counting":
+                extras[name] = run_counting(dev)
+                continue
+            if name == "u128":
+                extras[name] = run_u128(dev)
+                continue
             if name == "learned":
                 extras[name] = run_learned(max(3, args.steps // 2), 1, dev)
                 if "gmm_zscore" in extras:
@@ -646,7 +783,7 @@ def main():
                 continue
             es = EXTRAS[name]
             esteps = max(3, args.steps // 2)
-            ek, ems, est, ekt, ecfg = run_workload(es, esteps, 1, None, dev)
+            ek, ems, est, ekt, ecfg = run_workload(es, esteps, 1, None, dev, autotune=args.autotune)
             del ek
             epw = es["payload_bytes"]
             extras[name] = {

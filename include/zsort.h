@@ -99,6 +99,12 @@ enum {
  *                over the keys).  zsort_stable_ex and zsort_stable_segmented
  *                only; the debug, traced and learned entry points return
  *                ZSORT_EUNSUPPORTED for it.
+ *   count_range  0 (default: off) or 1..k: a subproblem whose keys span less
+ *                than count_range (max - min < count_range) is finished by one
+ *                stable counting pass on x - min (the counting-sort heuristic
+ *                for small ranges in Section III), in which every key value
+ *                is a cluster of its own, instead of further distribution
+ *                levels.  Output-neutral.
  */
 #define ZSORT_FLAG_GRAPH 1
 #define ZSORT_FLAG_SIGNED 2
@@ -109,7 +115,8 @@ typedef struct zsort_config {
   int32_t chunk;
   int32_t tile;
   int32_t flags;
-  int32_t reserved[2];
+  int32_t count_range;
+  int32_t reserved;
 } zsort_config;
 
 /* Fills cfg with the defaults above (k, the cutoff and the recursion depth
@@ -197,6 +204,35 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
                            const int64_t* seg_offsets, int32_t num_segments,
                            const zsort_config* cfg, void* stream);
 
+/*
+ * 128-bit keys (an extension named by the paper's motivation, Section I: the
+ * number of distribution passes does not grow with the key width, unlike a
+ * radix sort's).  keys: DEVICE array of n keys of 16 bytes, each the two u64
+ * words of an unsigned 128-bit integer, low word first; sorted in place,
+ * stably, with an optional u32 payload (may be NULL).  Two z-score stages
+ * over 64-bit words: the high words of all keys are sorted (Algorithm 1,
+ * Eq. (1)), each carrying its key's position; then every run of equal high
+ * words is sorted by its low words -- inside such a run the key rebased to
+ * the run's minimum fits 64 bits.  Runs of at most 64 keys are sorted at
+ * once by an insertion sort; longer ones by the same distribution as a batch
+ * of subproblems.  ZSORT_FLAG_SIGNED orders the keys as two's-complement
+ * int128; ZSORT_FLAG_GRAPH returns ZSORT_EUNSUPPORTED.  The stream keeps
+ * buffers of 24 bytes per key for the stages (plus the workspace of the
+ * 64-bit sort with a u32 payload).  report (host, may be NULL) makes the call
+ * synchronous and receives the recursion depth of each stage and the runs.
+ */
+typedef struct zsort_u128_report {
+  int32_t levels_high;   /* recursion levels of the high-word stage */
+  int32_t levels_low;    /* of the low-word stage (0: no run longer than 64 keys) */
+  uint64_t runs;         /* runs of >= 2 equal high words */
+  uint64_t short_runs;   /* of which <= 64 keys, sorted by insertion */
+  uint64_t run_keys;     /* keys in all runs */
+  int32_t device_error;  /* as zsort_stats.device_error, either stage */
+  int32_t reserved;
+} zsort_u128_report;
+int zsort_stable_u128(uint64_t* keys, uint32_t* payload, size_t n, const zsort_config* cfg,
+                      zsort_u128_report* report, void* stream);
+
 /* Device bytes of workspace a call of this shape needs (0 if invalid): the
  * ping-pong partner of keys and payload (Algorithm 1's second array), the
  * recursion's lists and the histogram rows.  cfg NULL: the configuration such
@@ -264,6 +300,8 @@ typedef struct zsort_stats {
   uint32_t segs_per_level[ZSORT_MAX_LEVELS];
   uint64_t local_keys;
   double model_bytes;
+  uint32_t counted;     /* subproblems finished by a counting pass (count_range) */
+  uint32_t reserved;
 } zsort_stats;
 
 int zsort_get_last_stats(void* stream, zsort_stats* out /* host */);
@@ -283,7 +321,7 @@ int zsort_debug_level0(const uint64_t* keys, const void* payload, int payload_by
 
 /*
  * Record of one subproblem larger than the cutoff, for level-by-level parity:
- * depth, kind (1 identical keys, 2 z-score map, 3 range map), position and
+ * depth, kind (1 identical keys, 2 z-score map, 3 range map, 4 counting pass), position and
  * size, exact moments about the minimum (S1: 2 limbs, S2: 4 limbs,
  * little-endian), the binary64 statistics of the map, the range-map shift,
  * the number of non-empty clusters and the offset of its k cluster counts in

@@ -59,6 +59,8 @@ def lib():
         L.zo_brute_stable_sort.argtypes = [P, P, I32, U64]
         L.zo_brute_stable_sort.restype = I32
         L.zo_seg_rec_size.restype = I32
+        L.zo_sort128.argtypes = [P, P, U64, I32]
+        L.zo_sort128.restype = I32
         L.zo_mlp_norm.argtypes = [U64, U64, U64]
         L.zo_mlp_norm.restype = D
         L.zo_mlp_forward.argtypes = [P, D]
@@ -209,6 +211,18 @@ def sort_segmented(keys, offsets, payload=None, k=1024, cutoff=96, max_zlevels=8
     if rc:
         raise ValueError("oracle rejected the arguments")
     return x, p
+
+
+def sort128(keys2, payload=None, signed=False):
+    """Stable sort of 128-bit keys (an (n, 2) u64 array, low word first) with
+    an optional u32 payload: the definition, written out (merge sort)."""
+    k = np.array(keys2, dtype=np.uint64, copy=True).reshape(-1, 2)
+    k = np.ascontiguousarray(k)
+    p = None if payload is None else np.array(payload, dtype=np.uint32, copy=True)
+    rc = lib().zo_sort128(k.ctypes.data, _ptr(p), k.shape[0], 1 if signed else 0)
+    if rc:
+        raise MemoryError("zo_sort128")
+    return k, p
 
 
 def brute_stable_sort(keys, payload=None):

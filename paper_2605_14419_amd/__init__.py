@@ -26,6 +26,7 @@ EXPORTED = [
     "zsort_debug_level0", "zsort_stable_traced", "zsort_release", "zsort_last_hip_error",
     "zsort_strerror", "zsort_profile_begin", "zsort_profile_begin_stages", "zsort_profile_end",
     "zsort_autotune", "zsort_set_workspace", "zsort_set_alloc_limit", "zsort_stable_noalloc",
+    "zsort_stable_u128",
     "zsort_default_learned_config", "zsort_stable_learned", "zsort_learned_sample",
     "zsort_mlp_forward", "zsort_mlp_thresholds", "zsort_mlp_init", "zsort_mlp_grad",
     "zsort_mlp_train",
@@ -44,7 +45,7 @@ class ZsortConfig(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("max_zlevels", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("count_range", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ZsortStats(ctypes.Structure):
@@ -56,7 +57,15 @@ class ZsortStats(ctypes.Structure):
                 ("mkeys_per_level", ctypes.c_uint64 * MAX_LEVELS),
                 ("segs_per_level", ctypes.c_uint32 * MAX_LEVELS),
                 ("local_keys", ctypes.c_uint64),
-                ("model_bytes", ctypes.c_double)]
+                ("model_bytes", ctypes.c_double),
+                ("counted", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ZsortU128Report(ctypes.Structure):
+    _fields_ = [("levels_high", ctypes.c_int32), ("levels_low", ctypes.c_int32),
+                ("runs", ctypes.c_uint64), ("short_runs", ctypes.c_uint64),
+                ("run_keys", ctypes.c_uint64), ("device_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ZsortLearnedConfig(ctypes.Structure):
@@ -117,6 +126,7 @@ def lib():
         L.zsort_stable_p64.argtypes = [P, P, Z, P]
         L.zsort_stable_ex.argtypes = [P, P, I, Z, P, P]
         L.zsort_stable_noalloc.argtypes = [P, P, I, Z, P, P]
+        L.zsort_stable_u128.argtypes = [P, P, Z, P, P, P]
         L.zsort_stable_segmented.argtypes = [P, P, I, Z, P, ctypes.c_int32, P, P]
         L.zsort_workspace_bytes.argtypes = [Z, I, ctypes.c_int32, P]
         L.zsort_set_workspace.argtypes = [P, Z, P]
@@ -233,6 +243,25 @@ def zsort_stable_noalloc(keys, payload=None, cfg=None, stream=None):
         _keys_ptr(keys), p, pw, keys.numel(), _cfg(cfg), _stream(stream)))
 
 
+def zsort_stable_u128(keys, payload=None, cfg=None, report=False, stream=None):
+    """128-bit keys: `keys` holds 2n u64 words (low word first per key, int64
+    or uint64 tensor of 2n elements); payload u32 or None.  Returns the report
+    as a dict when report=True (synchronous)."""
+    if keys.numel() % 2:
+        raise ValueError("128-bit keys need an even number of 64-bit words")
+    n = keys.numel() // 2
+    p, pw = _pay(payload, n)
+    if pw not in (0, 4):
+        raise ValueError("zsort_stable_u128 takes a 4-byte payload")
+    rep = ZsortU128Report() if report else None
+    _check("zsort_stable_u128", lib().zsort_stable_u128(
+        _keys_ptr(keys), p, n, _cfg(cfg), ctypes.byref(rep) if rep is not None else None,
+        _stream(stream)))
+    if rep is None:
+        return None
+    return {f: getattr(rep, f) for f, _ in ZsortU128Report._fields_ if f != "reserved"}
+
+
 def zsort_stable_segmented(keys, seg_offsets, payload=None, cfg=None, stream=None):
     import torch
     if (not seg_offsets.is_cuda or seg_offsets.dtype != torch.int64
@@ -277,7 +306,7 @@ def zsort_get_last_stats(stream=None) -> dict:
                 keys_per_level=list(s.keys_per_level[:L]),
                 mkeys_per_level=list(s.mkeys_per_level[:L]),
                 segs_per_level=list(s.segs_per_level[:L]), local_keys=s.local_keys,
-                model_bytes=s.model_bytes)
+                model_bytes=s.model_bytes, counted=s.counted)
 
 
 def zsort_debug_level0(keys, payload=None, cfg=None, stream=None):

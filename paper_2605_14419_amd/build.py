@@ -10,6 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libzsort.so")
 SOURCES = [os.path.join(CSRC, "zsort_kernels.hip"), os.path.join(CSRC, "zsort_learned.hip"),
+           os.path.join(CSRC, "zsort_wide.hip"),
            os.path.join(CSRC, "zsort_api.cpp")]
 
 HIPCC_FLAGS = [

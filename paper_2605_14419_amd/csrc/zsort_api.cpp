@@ -21,6 +21,17 @@ namespace zs {
 hipError_t launch_reset(const Ws& ws, hipStream_t st);
 hipError_t launch_clear_rows(const Ws& ws, int grid, hipStream_t st);
 hipError_t scratch_address(int dev, void** out);
+hipError_t launch_init_runs(const Ws& ws, const uint32_t* runs, const uint32_t* nruns, int grid,
+                            hipStream_t st);
+hipError_t launch_split128(const uint64_t* keys, const uint32_t* payload, uint64_t n, int sgn,
+                           uint64_t* hi, uint32_t* idx, uint32_t* pay_copy, uint32_t* nruns,
+                           int grid, hipStream_t st);
+hipError_t launch_gather_runs(const uint64_t* keys, const uint64_t* hi, uint32_t* idx, uint64_t n,
+                              uint64_t* lo, uint32_t* runs, uint32_t* nruns, int grid,
+                              hipStream_t st);
+hipError_t launch_final128(uint64_t* keys, uint32_t* payload, uint64_t n, int sgn,
+                           const uint64_t* hi, const uint64_t* lo, const uint32_t* idx,
+                           const uint32_t* pay_copy, int grid, hipStream_t st);
 hipError_t launch_check_sorted(const uint64_t* keys, uint64_t n, uint32_t* flag, int grid,
                                hipStream_t st);
 hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st);
@@ -156,11 +167,11 @@ struct GraphKey {
   const void* off;
   uint64_t n;
   int32_t nseg;
-  int pw, k, cutoff, maxz, chunk, tile, flags;
+  int pw, k, cutoff, maxz, chunk, tile, flags, count_range;
   bool operator<(const GraphKey& o) const {
-    return std::tie(keys, pay, off, n, nseg, pw, k, cutoff, maxz, chunk, tile, flags) <
+    return std::tie(keys, pay, off, n, nseg, pw, k, cutoff, maxz, chunk, tile, flags, count_range) <
            std::tie(o.keys, o.pay, o.off, o.n, o.nseg, o.pw, o.k, o.cutoff, o.maxz, o.chunk, o.tile,
-                    o.flags);
+                    o.flags, o.count_range);
   }
 };
 
@@ -253,6 +264,7 @@ int check_cfg(const zsort_config* c) {
   if (c->tile != 2048 && c->tile != 4096 && c->tile != 8192) return ZSORT_EINVAL;
   if (c->tile > 2048 && (c->k > 1024 || c->chunk % c->tile)) return ZSORT_EINVAL;
   if (c->tile == 8192 && c->chunk > 65536) return ZSORT_EINVAL;
+  if (c->count_range < 0 || c->count_range > c->k) return ZSORT_EINVAL;
   return ZSORT_OK;
 }
 
@@ -373,6 +385,7 @@ Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay
   ws.p.chunk = c.chunk;
   ws.p.tile = c.tile;
   ws.p.pw = pw;
+  ws.p.count_range = c.count_range;
   return ws;
 }
 
@@ -405,6 +418,11 @@ struct Call {
   bool level0_only;
   int slot = 0;    // 1: the auxiliary workspace (sample sorts of the learned map)
   int kfirst = 0;  // clusters of a learned first pass the workspace must also hold
+  // subproblems given as a device list of (start, length) pairs instead of
+  // one array or a partition: *nruns of them, at most runs_cap
+  const uint32_t* runs = nullptr;
+  const uint32_t* nruns = nullptr;
+  int64_t runs_cap = 0;
 };
 
 // pinned count buffer and per-level events, created once per workspace
@@ -448,7 +466,7 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   s.cutoff = c.cfg.cutoff;
   s.chunk = c.cfg.chunk;
   s.tile = c.cfg.tile;
-  s.nseg = c.off ? c.nseg : 0;
+  s.nseg = c.off ? c.nseg : (c.runs ? c.runs_cap : 0);
   s.trace_cap = c.trace_cap;
   s.trace_hist_cap = c.hist_cap;
   s.kfirst = c.kfirst;
@@ -459,10 +477,11 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   hipError_t e = prepare_rows(w, &ws, st);
   if (e != hipSuccess) return hip_fail(e);
   const bool graph = (c.cfg.flags & ZSORT_FLAG_GRAPH) && !c.level0_only && !c.trace_cap &&
-                     !capturing(st);
+                     !c.runs && !capturing(st);
   if (graph) {
     GraphKey gk{c.keys, c.pay, c.off, c.n, c.off ? c.nseg : 0, c.pw, c.cfg.k, c.cfg.cutoff,
-                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile, c.cfg.flags & ZSORT_FLAG_SIGNED};
+                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile, c.cfg.flags & ZSORT_FLAG_SIGNED,
+                c.cfg.count_range};
     auto it = w->graphs.find(gk);
     hipGraphExec_t ex = nullptr;
     if (it != w->graphs.end()) {
@@ -512,7 +531,8 @@ hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
   hipError_t e = sgn ? zs::launch_flip(c.keys, c.n, fgrid, st) : hipSuccess;
   if (e == hipSuccess) e = zs::launch_reset(ws, st);
   if (e == hipSuccess) {
-    if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
+    if (c.runs) e = zs::launch_init_runs(ws, c.runs, c.nruns, std::max(1, g_cu_count) * 4, st);
+    else if (c.off) e = zs::launch_init_segments(ws, c.off, c.nseg, c.n, st);
     else e = zs::launch_init_single(ws, c.n, st);
   }
   if (e == hipSuccess) e = enqueue_levels(w, ws, c, st, 0);
@@ -851,6 +871,144 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
   return run(call, (hipStream_t)stream, nullptr);
 }
 
+// ---- 128-bit keys ----------------------------------------------------------
+}  // extern "C"
+namespace {
+// buffers of the two stages of a 128-bit sort, per stream (grown, never shrunk)
+struct WideWs {
+  char* base = nullptr;
+  uint64_t n_cap = 0;
+  uint64_t* hi = nullptr;
+  uint64_t* lo = nullptr;
+  uint32_t* idx = nullptr;
+  uint32_t* pay = nullptr;
+  uint32_t* runs = nullptr;
+  uint32_t* counters = nullptr;  // [0] runs, [2..3] keys in runs (u64)
+};
+std::unordered_map<hipStream_t, WideWs*> g_wide;
+
+int wide_acquire(hipStream_t st, uint64_t n, WideWs** out) {
+  WideWs*& w = g_wide[st];
+  if (!w) w = new WideWs();
+  if (w->base && n <= w->n_cap) {
+    *out = w;
+    return ZSORT_OK;
+  }
+  if (capturing(st)) return ZSORT_ECAPTURE;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = align_up(o, 256);
+    o = at + b;
+    return at;
+  };
+  const uint64_t nr = n / 65 + 1;   // runs of > 64 keys
+  const size_t o_hi = take(n * 8), o_lo = take(n * 8), o_idx = take(n * 4), o_pay = take(n * 4),
+               o_runs = take(nr * 8), o_cnt = take(16);
+  if (w->base) {
+    hipError_t e = hipFree(w->base);
+    w->base = nullptr;
+    w->n_cap = 0;
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  void* p = nullptr;
+  hipError_t e = dev_alloc(&p, align_up(o, 256));
+  if (e != hipSuccess) return hip_fail(e);
+  char* b = (char*)p;
+  w->base = b;
+  w->n_cap = n;
+  w->hi = (uint64_t*)(b + o_hi);
+  w->lo = (uint64_t*)(b + o_lo);
+  w->idx = (uint32_t*)(b + o_idx);
+  w->pay = (uint32_t*)(b + o_pay);
+  w->runs = (uint32_t*)(b + o_runs);
+  w->counters = (uint32_t*)(b + o_cnt);
+  *out = w;
+  return ZSORT_OK;
+}
+
+// levels with work in the control block of the stream's workspace (the
+// stream must have reached the call)
+int ctl_levels(hipStream_t st, int32_t* levels, int32_t* err) {
+  auto it = g_ws.find(st);
+  if (it == g_ws.end()) return ZSORT_EINVAL;
+  zs::Ctl ctl;
+  hipError_t e = hipMemcpy(&ctl, it->second->base + it->second->lay.off_ctl, sizeof ctl,
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  int L = 0;
+  for (int i = 0; i < zs::kMaxLevels; ++i)
+    if (ctl.lvl_mkeys[i]) L = i + 1;
+  *levels = L;
+  *err |= (int32_t)ctl.error;
+  return ZSORT_OK;
+}
+}  // namespace
+extern "C" {
+
+int zsort_stable_u128(uint64_t* keys, uint32_t* payload, size_t n, const zsort_config* cfg,
+                      zsort_u128_report* report, void* stream) {
+  if (report) std::memset(report, 0, sizeof *report);
+  if (n > 0x7FFFFFFFull || (n > 1 && !keys)) return ZSORT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  zsort_config c;
+  int rc = resolve_cfg(cfg, &c, n, 4, 0);
+  if (rc) return rc;
+  if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
+  if (n <= 1) return ZSORT_OK;
+  const int sgn = (c.flags & ZSORT_FLAG_SIGNED) ? 1 : 0;
+  c.flags &= ~ZSORT_FLAG_SIGNED;   // the high words are flipped by the split itself
+  hipStream_t st = (hipStream_t)stream;
+  WideWs* w = nullptr;
+  rc = wide_acquire(st, n, &w);
+  if (rc) return rc;
+  if (!g_cu_count) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  const int grid = std::max(1, g_cu_count) * 8;
+  // stage 1: the high words, each carrying its key's position
+  hipError_t e = zs::launch_split128(keys, payload, n, sgn, w->hi, w->idx, w->pay, w->counters,
+                                     grid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  Call hc{w->hi, w->idx, 4, (uint64_t)n, nullptr, 0, c, 0, 0, false};
+  rc = run(hc, st, nullptr);
+  if (rc) return rc;
+  if (report) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e);
+    rc = ctl_levels(st, &report->levels_high, &report->device_error);
+    if (rc) return rc;
+  }
+  // stage 2: the low words inside every run of equal high words (the key
+  // rebased to the run's minimum fits 64 bits there)
+  e = zs::launch_gather_runs(keys, w->hi, w->idx, n, w->lo, w->runs, w->counters, grid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  Call lc{w->lo, w->idx, 4, (uint64_t)n, nullptr, 0, c, 0, 0, false};
+  lc.runs = w->runs;
+  lc.nruns = w->counters;
+  lc.runs_cap = (int64_t)(n / 65 + 1);
+  rc = run(lc, st, nullptr);
+  if (rc) return rc;
+  e = zs::launch_final128(keys, payload, n, sgn, w->hi, w->lo, w->idx, w->pay, grid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (report) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e);
+    rc = ctl_levels(st, &report->levels_low, &report->device_error);
+    if (rc) return rc;
+    uint32_t cnt[4] = {0, 0, 0, 0};
+    e = hipMemcpy(cnt, w->counters, sizeof cnt, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    report->runs = (uint64_t)cnt[0] + cnt[1];
+    report->short_runs = cnt[1];
+    report->run_keys = (uint64_t)cnt[2] | ((uint64_t)cnt[3] << 32);
+  }
+  return ZSORT_OK;
+}
+
 size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
                              const zsort_config* cfg) {
   if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return 0;
@@ -937,6 +1095,7 @@ int zsort_get_last_stats(void* stream, zsort_stats* out) {
   }
   bytes += 2 * kp * (double)ctl.local_keys + w->last_extra_bytes;
   out->local_keys = ctl.local_keys;
+  out->counted = ctl.n_count;
   out->levels = levels;
   out->model_bytes = bytes;
   return ZSORT_OK;
@@ -1177,6 +1336,14 @@ int zsort_release(void) {
   g_ws.clear();
   for (auto& kv : g_ws_aux) free_ws(kv.second);
   g_ws_aux.clear();
+  for (auto& kv : g_wide) {
+    if (kv.second->base) {
+      hipError_t e = hipFree(kv.second->base);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    delete kv.second;
+  }
+  g_wide.clear();
   for (auto& kv : g_lws) {
     if (kv.second->base) {
       hipError_t e = hipFree(kv.second->base);

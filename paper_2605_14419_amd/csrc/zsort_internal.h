@@ -65,7 +65,12 @@ enum : int { STAGE_MOMENTS = 0, STAGE_FINALIZE = 1, STAGE_HIST = 2, STAGE_SCATTE
 
 // segment kinds, as in the recursion records; KIND_LMAP is the learned
 // partition map of the first pass (bucket ids precomputed by the hist pass)
-enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3, KIND_LMAP = 4 };
+// KIND_COUNT: a counting pass (key range below count_range): the clusters are
+// the key values themselves, so each is final after the scatter
+enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3, KIND_LMAP = 4,
+                 KIND_COUNT = 5 };
+// kind of a counting pass in the recursion records of the public trace
+constexpr int32_t kTraceCount = 4;
 // segment flags
 enum : uint32_t { F_RMAP = 1u, F_ROOT = 2u };
 // leaf-group flags
@@ -127,6 +132,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t n_leafgroups;
   uint32_t max_level;
   uint64_t local_keys;           // keys sorted or copied by the local kernel
+  uint32_t n_count;              // subproblems finished by a counting pass
 };
 
 enum : uint32_t { ERR_SEGCAP = 1u, ERR_WORKCAP = 2u, ERR_LEAFCAP = 4u, ERR_STATUSCAP = 8u,
@@ -201,6 +207,7 @@ struct Params {
   int32_t chunk;         // keys per work item
   int32_t tile;          // keys per scatter tile (2048, 4096 or 8192)
   int32_t pw;            // payload bytes: 0, 4, 8
+  int32_t count_range;   // > 0: subproblems with max - min < count_range take a counting pass
 };
 
 // Everything a kernel needs, by value.

@@ -387,6 +387,8 @@ struct MapP {
 __device__ __forceinline__ MapP map_of(const Seg& s, int k) {
   MapP p;
   p.o = s.o; p.m = s.m; p.A = s.A; p.B = s.B; p.k = k; p.kind = s.kind; p.shift = s.shift;
+  // a counting pass is the exact range map with every key value a cluster
+  if (s.kind == KIND_COUNT) { p.kind = KIND_RMAP; p.shift = 0; }
   return p;
 }
 
@@ -533,6 +535,7 @@ __global__ void k_reset(Ws ws) {
     c->ntrace = 0;
     c->ntrace_hist = 0;
     c->n_ident = c->n_rmap = c->n_leafgroups = 0;
+    c->n_count = 0;
     c->max_level = 0;
     c->local_keys = 0;
   }
@@ -697,40 +700,54 @@ __global__ void k_check_offsets(Ws ws, const int64_t* off, int32_t nseg, uint64_
   }
 }
 
+// independent subproblem [a, a + len) of level 0 (one array of a batch, or
+// one run of equal high words of 128-bit keys): a leaf, or a root segment
+// with its work items and tiles
+__device__ void init_root(Ws& ws, uint64_t a, uint64_t len) {
+  Ctl* c = ws.ctl;
+  const uint64_t ch = (uint64_t)ws.p.chunk;
+  if (len <= 1) return;
+  if (len <= (uint64_t)ws.p.cutoff) {
+    push_leaf(ws, 0, a, (uint32_t)len, 0u, 0u);
+    atomicAdd(&c->n_leafgroups, 1u);
+    return;
+  }
+  const uint32_t nch = (uint32_t)((len + ch - 1) / ch);
+  uint32_t si = atomicAdd(&c->nseg[0], 1u);
+  uint32_t wi = atomicAdd(&c->nwork[0], nch);
+  uint32_t sb = nch > 1 ? atomicAdd(&c->nstatus[0], status_rows(nch)) : 0u;
+  if (si >= ws.seg_cap || wi + nch > ws.work_cap || sb + status_rows(nch) > ws.status_cap) {
+    atomicOr(&c->error, ERR_SEGCAP);
+    return;
+  }
+  make_root_seg(ws, si, a, len, wi, nch, sb);
+  clear_arrivals(ws.arrive[0] + sb, nch);
+  for (uint32_t j = 0; j < nch; ++j) ws.work[0][wi + j] = ((uint64_t)si << 32) | j;
+  const uint32_t nsub = tiles_per_item(ws);
+  if (nsub > 1) {
+    const uint32_t ntl = (uint32_t)((len + 8191) >> 13);
+    const uint32_t ti = atomicAdd(&c->ntile[0], ntl);
+    if (ti + ntl > ws.tile_cap) {
+      atomicOr(&c->error, ERR_WORKCAP);
+      return;
+    }
+    for (uint32_t u = 0; u < ntl; ++u) ws.tiles[0][ti + u] = tile_entry(si, u, nsub);
+  }
+}
+
 __global__ void k_init_segments(Ws ws, const int64_t* off, int32_t nseg) {
   Ctl* c = ws.ctl;
   if (__hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const uint64_t ch = (uint64_t)ws.p.chunk;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
-    const uint64_t a = (uint64_t)off[i], len = (uint64_t)(off[i + 1] - off[i]);
-    if (len <= 1) continue;
-    if (len <= (uint64_t)ws.p.cutoff) {
-      push_leaf(ws, 0, a, (uint32_t)len, 0u, 0u);
-      atomicAdd(&c->n_leafgroups, 1u);
-      continue;
-    }
-    const uint32_t nch = (uint32_t)((len + ch - 1) / ch);
-    uint32_t si = atomicAdd(&c->nseg[0], 1u);
-    uint32_t wi = atomicAdd(&c->nwork[0], nch);
-    uint32_t sb = nch > 1 ? atomicAdd(&c->nstatus[0], status_rows(nch)) : 0u;
-    if (si >= ws.seg_cap || wi + nch > ws.work_cap || sb + status_rows(nch) > ws.status_cap) {
-      atomicOr(&c->error, ERR_SEGCAP);
-      continue;
-    }
-    make_root_seg(ws, si, a, len, wi, nch, sb);
-    clear_arrivals(ws.arrive[0] + sb, nch);
-    for (uint32_t j = 0; j < nch; ++j) ws.work[0][wi + j] = ((uint64_t)si << 32) | j;
-    const uint32_t nsub = tiles_per_item(ws);
-    if (nsub > 1) {
-      const uint32_t ntl = (uint32_t)((len + 8191) >> 13);
-      const uint32_t ti = atomicAdd(&c->ntile[0], ntl);
-      if (ti + ntl > ws.tile_cap) {
-        atomicOr(&c->error, ERR_WORKCAP);
-        continue;
-      }
-      for (uint32_t u = 0; u < ntl; ++u) ws.tiles[0][ti + u] = tile_entry(si, u, nsub);
-    }
-  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x)
+    init_root(ws, (uint64_t)off[i], (uint64_t)(off[i + 1] - off[i]));
+}
+
+// subproblems given as (start, length) pairs, *nruns of them (device count)
+__global__ void k_init_runs(Ws ws, const uint32_t* runs, const uint32_t* nruns) {
+  clear_rows_if_due(ws);
+  const uint32_t nr = *nruns;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x)
+    init_root(ws, runs[2 * i], runs[2 * i + 1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -754,7 +771,7 @@ __device__ void trace_ident(Ws& ws, const Seg& s) {
 // queue up behind each other)
 struct FinStat {
   uint64_t mkeys = 0;
-  uint32_t ident = 0, rmap = 0;
+  uint32_t ident = 0, rmap = 0, count = 0;
 };
 
 // acc: the segment's 32-bit digit sums a0..a5 (of x^2), b0, b1 (of x), then min, max
@@ -803,6 +820,16 @@ __device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10], FinSt
   }
 
   const int k = ws.p.k;
+  if (ws.p.count_range > 0 && M - o < (uint64_t)ws.p.count_range) {
+    // a small key range (the counting-sort heuristic of Section III): one
+    // stable counting pass on x - o finishes the subproblem (count_range <= k,
+    // so every value has a cluster of its own)
+    s.m = s.sigma = s.zmin = s.A = s.B = 0.0;
+    s.shift = 0;
+    s.kind = KIND_COUNT;
+    ++fs.count;
+    return;
+  }
   bool rmap = (s.flags & F_RMAP) != 0;
   double m = 0, sigma = 0, zmin = 0, A = 0, B = 0;
   if (!rmap) {
@@ -982,16 +1009,18 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   }
   // statistics of the wave's segments
   uint64_t mk = fs.mkeys;
-  uint32_t id = fs.ident, rm = fs.rmap;
+  uint32_t id = fs.ident, rm = fs.rmap, ct = fs.count;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
     mk += __shfl_xor(mk, d);
     id += __shfl_xor(id, d);
     rm += __shfl_xor(rm, d);
+    ct += __shfl_xor(ct, d);
   }
   if (ln == 0) {
     if (mk) atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)mk);
     if (id) atomicAdd(&c->n_ident, id);
+    if (ct) atomicAdd(&c->n_count, ct);
     if (rm) atomicAdd(&c->n_rmap, rm);
   }
 }
@@ -1035,12 +1064,14 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   const uint64_t sg_start = sg.start, sg_count = sg.count, sg_o = sg.o;
   const double sg_m = sg.m, sg_sigma = sg.sigma, sg_zmin = sg.zmin;
   const int32_t sg_kind = sg.kind;
+  // a counting pass: every cluster holds one key value and is final
+  const bool counted = sg_kind == KIND_COUNT;
 
   // exclusive cluster starts, and per child: index, chunk offset, scan row
   // offset, tile offset -- five scans in one pass
   for (int b = t; b < k; b += kBlock) {
     const uint32_t n = sm.h[b];
-    const bool child = n > cutoff;
+    const bool child = !counted && n > cutoff;
     const uint32_t nch = child ? (n + ch - 1) / ch : 0u;
     sm.bst[b] = n;
     sm.t0[b] = child ? 1u : 0u;
@@ -1092,7 +1123,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   if (fits) {
     for (int b = t; b < k; b += kBlock) {
       const uint32_t n = sm.h[b];
-      if (n <= cutoff) continue;
+      if (n <= cutoff || counted) continue;
       const uint32_t idx = sm.base_seg + sm.t0[b];
       Seg& cs = ws.segs[N][idx];
       const bool crm = !(parent_l && ws.lm.sub) &&
@@ -1132,7 +1163,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
     __syncthreads();
     // child list: position by child index
     for (int b = t; b < k; b += kBlock)
-      if (sm.h[b] > cutoff) sm.t2[sm.t0[b]] = (uint32_t)b;  // t2 reused: child -> bucket
+      if (!counted && sm.h[b] > cutoff) sm.t2[sm.t0[b]] = (uint32_t)b;  // t2 reused: child -> bucket
     __syncthreads();
     // work items and (8192-key tiles) scatter tiles, child by child in
     // chunk order: a wave per child, its lanes over the child's entries
@@ -1200,82 +1231,93 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   }
   __syncthreads();
 
-  // leaf groups: consecutive leaf clusters of one run (no child cluster in
-  // between) whose starts fall in one window [w*kWindow, (w+1)*kWindow) form
-  // one group of < 2*kWindow keys; a leaf larger than kWindow is a group of
-  // its own.  Clusters are ordered (max of one < min of the next), so sorting
-  // a group as a whole equals sorting each cluster.
-  int* prev = (int*)sm.t0;
-  for (int b = t; b < k; b += kBlock) prev[b] = sm.h[b] ? b : -1;
-  __syncthreads();
-  block_excl_max_lds(prev, k, (int*)sm.sh);
-  for (int b = t; b < k; b += kBlock) {
-    const uint32_t n = sm.h[b];
-    uint32_t boundary = 0;
-    if (n > cutoff) boundary = 1;
-    else if (n > 0) {
-      const int pb = prev[b];
-      if (pb < 0 || sm.h[pb] > cutoff || sm.h[pb] > (uint32_t)kWindow || n > (uint32_t)kWindow ||
-          sm.bst[pb] / (uint32_t)kWindow != sm.bst[b] / (uint32_t)kWindow)
-        boundary = 2;
+  if (counted) {
+    // the segment is sorted once this level's scatter has run; from the
+    // alternate buffer it is copied home in pieces
+    if (N == 1)
+      for (uint64_t a = (uint64_t)t * kCopyChunk; a < sg_count; a += (uint64_t)kBlock * kCopyChunk)
+        if (!push_leaf(ws, S, sg_start + a, (uint32_t)min((uint64_t)kCopyChunk, sg_count - a),
+                       LF_COPY, 1u))
+          break;
+    __syncthreads();
+  } else {
+    // leaf groups: consecutive leaf clusters of one run (no child cluster in
+    // between) whose starts fall in one window [w*kWindow, (w+1)*kWindow) form
+    // one group of < 2*kWindow keys; a leaf larger than kWindow is a group of
+    // its own.  Clusters are ordered (max of one < min of the next), so sorting
+    // a group as a whole equals sorting each cluster.
+    int* prev = (int*)sm.t0;
+    for (int b = t; b < k; b += kBlock) prev[b] = sm.h[b] ? b : -1;
+    __syncthreads();
+    block_excl_max_lds(prev, k, (int*)sm.sh);
+    for (int b = t; b < k; b += kBlock) {
+      const uint32_t n = sm.h[b];
+      uint32_t boundary = 0;
+      if (n > cutoff) boundary = 1;
+      else if (n > 0) {
+        const int pb = prev[b];
+        if (pb < 0 || sm.h[pb] > cutoff || sm.h[pb] > (uint32_t)kWindow || n > (uint32_t)kWindow ||
+            sm.bst[pb] / (uint32_t)kWindow != sm.bst[b] / (uint32_t)kWindow)
+          boundary = 2;
+      }
+      sm.t1[b] = boundary;
     }
-    sm.t1[b] = boundary;
-  }
-  __syncthreads();
-  for (int b = t; b < k; b += kBlock) sm.t2[b] = sm.t1[b] ? 1u : 0u;
-  __syncthreads();
-  const uint32_t nb = block_scan_lds(sm.t2, k, sm.sh);
-  // compacted boundaries in cluster order: start position, top bit = group start
-  uint32_t* bpos = sm.t0;
-  for (int b = t; b < k; b += kBlock)
-    if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
-  __syncthreads();
-  const uint32_t wcap = (uint32_t)wave_job_cap(ws.p.pw);
-  uint32_t my_small = 0, my_mid = 0, my_big = 0;
-  for (uint32_t i = t; i < nb; i += kBlock) {
-    if (!(bpos[i] >> 31)) continue;
-    const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
-    const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
-    if (p1 - p0 <= wcap) ++my_small;
-    else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
-    else ++my_big;
-  }
-  const uint32_t mine[3] = {my_small, my_mid, my_big};
-  uint32_t offs[3], tots[3];
-  block_excl_sum3(mine, sm.shm, offs, tots);
-  const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2];
-  const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2];
-  // the three leaf lists, likewise in one atomic instruction
-  if (t < 3) {
-    uint32_t* ctr = t == 0 ? &c->nleafw[S] : (t == 1 ? &c->nleafm[S] : &c->nleaf[S]);
-    const uint32_t v = t == 0 ? nsmall : (t == 1 ? nmid : nbig);
-    const uint32_t r = v ? atomicAdd(ctr, v) : 0u;
-    // (base_status is reused as the big-list base)
-    uint32_t* out = t == 0 ? &sm.base_leaf : (t == 1 ? &sm.base_mid : &sm.base_status);
-    *out = r;
-  }
-  if (t == 0) sm.st_groups += nsmall + nmid + nbig;
-  __syncthreads();
-  if (t == 0 && (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
-                 sm.base_status + nbig > ws.leaf_cap))
-    atomicOr(&c->error, ERR_LEAFCAP);
-  if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
-      sm.base_status + nbig <= ws.leaf_cap) {
-    uint32_t os = sm.base_leaf + off_small, om = sm.base_mid + off_mid, ob = sm.base_status + off_big;
+    __syncthreads();
+    for (int b = t; b < k; b += kBlock) sm.t2[b] = sm.t1[b] ? 1u : 0u;
+    __syncthreads();
+    const uint32_t nb = block_scan_lds(sm.t2, k, sm.sh);
+    // compacted boundaries in cluster order: start position, top bit = group start
+    uint32_t* bpos = sm.t0;
+    for (int b = t; b < k; b += kBlock)
+      if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
+    __syncthreads();
+    const uint32_t wcap = (uint32_t)wave_job_cap(ws.p.pw);
+    uint32_t my_small = 0, my_mid = 0, my_big = 0;
     for (uint32_t i = t; i < nb; i += kBlock) {
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
       const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
-      const bool small = p1 - p0 <= wcap;
-      const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
-      Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
-      lf.start = (uint32_t)(sg_start + p0);
-      lf.count = p1 - p0;
-      lf.flags = 0;
-      lf.src = (uint32_t)N;  // written by this level's scatter
+      if (p1 - p0 <= wcap) ++my_small;
+      else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
+      else ++my_big;
     }
+    const uint32_t mine[3] = {my_small, my_mid, my_big};
+    uint32_t offs[3], tots[3];
+    block_excl_sum3(mine, sm.shm, offs, tots);
+    const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2];
+    const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2];
+    // the three leaf lists, likewise in one atomic instruction
+    if (t < 3) {
+      uint32_t* ctr = t == 0 ? &c->nleafw[S] : (t == 1 ? &c->nleafm[S] : &c->nleaf[S]);
+      const uint32_t v = t == 0 ? nsmall : (t == 1 ? nmid : nbig);
+      const uint32_t r = v ? atomicAdd(ctr, v) : 0u;
+      // (base_status is reused as the big-list base)
+      uint32_t* out = t == 0 ? &sm.base_leaf : (t == 1 ? &sm.base_mid : &sm.base_status);
+      *out = r;
+    }
+    if (t == 0) sm.st_groups += nsmall + nmid + nbig;
+    __syncthreads();
+    if (t == 0 && (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
+                   sm.base_status + nbig > ws.leaf_cap))
+      atomicOr(&c->error, ERR_LEAFCAP);
+    if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
+        sm.base_status + nbig <= ws.leaf_cap) {
+      uint32_t os = sm.base_leaf + off_small, om = sm.base_mid + off_mid, ob = sm.base_status + off_big;
+      for (uint32_t i = t; i < nb; i += kBlock) {
+        if (!(bpos[i] >> 31)) continue;
+        const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
+        const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
+        const bool small = p1 - p0 <= wcap;
+        const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
+        Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
+        lf.start = (uint32_t)(sg_start + p0);
+        lf.count = p1 - p0;
+        lf.flags = 0;
+        lf.src = (uint32_t)N;  // written by this level's scatter
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // largest final cluster of the learned map (with two stages, root
   // clusters that are not split again count whole)
@@ -1305,7 +1347,8 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       sm.base_leaf = (ho + (uint32_t)k <= ws.trace_hist_cap) ? ho : 0xFFFFFFFFu;
       if (i < ws.trace_cap) {
         TraceRec& r = ws.trace[i];
-        r.depth = sg.depth; r.kind = sg.kind; r.start = sg.start; r.count = sg.count;
+        r.depth = sg.depth; r.kind = counted ? kTraceCount : sg.kind;
+        r.start = sg.start; r.count = sg.count;
         r.o = sg.o; r.M = sg.M;
         r.s1[0] = sg.s1[0]; r.s1[1] = sg.s1[1];
         for (int j = 0; j < 4; ++j) r.s2[j] = sg.s2[j];
@@ -2630,6 +2673,12 @@ hipError_t launch_reset_lists(const Ws& ws, int slot, hipStream_t st) {
 
 hipError_t launch_init_learned(const Ws& ws, uint64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_init_learned, dim3(64), dim3(kBlock), 0, st, ws, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_runs(const Ws& ws, const uint32_t* runs, const uint32_t* nruns, int grid,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_init_runs, dim3(grid), dim3(kBlock), 0, st, ws, runs, nruns);
   return hipGetLastError();
 }
 

@@ -18,4 +18,8 @@ from .gen import (  # noqa: F401
     segments,
     make,
     WORKLOADS,
+    small_range,
+    clustered_ranges,
+    make128,
+    WORKLOADS128,
 )

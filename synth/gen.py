@@ -142,6 +142,27 @@ def segments(nseg: int, seed: int, median: float = 2e4, sigma_ln: float = 1.0,
     return keys, off, idx
 
 
+def small_range(n: int, seed: int, span: int = 200) -> np.ndarray:
+    """Restricted range: keys uniform over [b, b + span) for a random base b
+    (the high-duplicate family of the paper draws from a restricted range)."""
+    rng = _rng(seed)
+    base = int(rng.integers(0, 2**64 - span, dtype=np.uint64))
+    return (np.uint64(base) + rng.integers(0, span, size=n, dtype=np.uint64)).astype(np.uint64)
+
+
+def clustered_ranges(n: int, seed: int, clusters: int = 20, span: int = 150) -> np.ndarray:
+    """Half the keys uniform over [0, 2^64), half in `clusters` narrow ranges
+    of `span` values at random places (small ranges show up below the root)."""
+    rng = _rng(seed)
+    out = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    bases = rng.integers(0, 2**64 - span, size=clusters, dtype=np.uint64)
+    pick = rng.random(n) < 0.5
+    m = int(pick.sum())
+    out[pick] = bases[rng.integers(0, clusters, size=m)] + rng.integers(0, span, size=m,
+                                                                           dtype=np.uint64)
+    return out
+
+
 # name -> (workload index, variant, generator)
 WORKLOADS = {
     "uniform_2p20": (0, 0, uniform),
@@ -155,6 +176,8 @@ WORKLOADS = {
     "gmm": (4, 0, gmm),
     "gmm_identity": (4, 1, lambda n, s: gmm(n, s, perm=(0, 1, 2, 3))),
     "uniform_1e8": (5, 0, uniform),
+    "small_range": (6, 0, small_range),
+    "clustered_ranges": (6, 1, clustered_ranges),
 }
 
 
@@ -171,3 +194,40 @@ def make(name: str, n: int, payload_bytes: int = 4):
     else:
         raise ValueError("payload_bytes must be 0, 4 or 8")
     return keys, pay
+
+
+# ---------------------------------------------------------------------------
+# 128-bit keys: (n, 2) u64 arrays, low word first
+# ---------------------------------------------------------------------------
+WORKLOADS128 = {"uuid": 0, "prefix": 1, "narrow": 2, "zext": 3, "dup": 4}
+
+
+def make128(name: str, n: int):
+    """keys (n, 2) u64 [lo, hi] and the u32 index payload.
+    uuid   -- both words i.i.d. uniform (random 128-bit identifiers)
+    prefix -- high word from 1000 distinct uniform values, low word uniform
+              (runs of equal high words of ~n/1000 keys)
+    narrow -- high word from n/20 distinct values (runs of ~20 keys)
+    zext   -- high word 0, low word lognormal as the 64-bit lognormal family
+              (one run: the whole array)
+    dup    -- 500 distinct (high, low) pairs, keys uniform among them"""
+    seed = seed_for(7, WORKLOADS128[name])
+    rng = _rng(seed)
+    k = np.empty((n, 2), dtype=np.uint64)
+    if name == "uuid":
+        k[:, 0] = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+        k[:, 1] = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    elif name in ("prefix", "narrow"):
+        d = 1000 if name == "prefix" else max(1, n // 20)
+        vals = rng.integers(0, 2**64, size=d, dtype=np.uint64, endpoint=False)
+        k[:, 1] = vals[rng.integers(0, d, size=n)]
+        k[:, 0] = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    elif name == "zext":
+        k[:, 1] = 0
+        k[:, 0] = lognormal(n, seed)
+    elif name == "dup":
+        vals = rng.integers(0, 2**64, size=(500, 2), dtype=np.uint64, endpoint=False)
+        k[:] = vals[rng.integers(0, 500, size=n)]
+    else:
+        raise KeyError(name)
+    return k, np.arange(n, dtype=np.uint32)

@@ -128,3 +128,13 @@ def test_scan_row_tags_are_distinct_and_nonzero_between_clears():
         t = t.reshape(-1)
         assert t.min() >= 1 and t.max() < 2**22
         assert np.unique(t).size == t.size, e0
+
+
+def test_count_range_must_not_exceed_k():
+    L = zs.lib()
+    bad = zs.zsort_default_config(k=256, count_range=257)
+    assert L.zsort_stable_ex(ctypes.c_void_p(16), None, 0, 10, ctypes.byref(bad), None) \
+        == zs.ZSORT_EINVAL
+    neg = zs.zsort_default_config(count_range=-1)
+    assert L.zsort_stable_ex(ctypes.c_void_p(16), None, 0, 10, ctypes.byref(neg), None) \
+        == zs.ZSORT_EINVAL

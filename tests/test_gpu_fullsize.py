@@ -1,6 +1,7 @@
 """GPU tests at the full sizes of the benchmark's workloads, in the
-configurations the benchmark runs (the library's autotuner picks k, tile,
-chunk and cutoff for each shape class, as bench.py does).
+configurations the benchmark runs (its recorded configuration per single-array
+workload; the library's autotuner for the batched and learned forms, as
+bench.py does).
 
 A stable sort has one correct output, which three properties pin without a
 reference sort: non-decreasing keys, an index payload that is a permutation
@@ -11,6 +12,7 @@ single array of 2^20 keys is compared with the CPU oracle bit for bit.
 import numpy as np
 import pytest
 
+import bench
 import oracle
 import synth
 from tests.invariants import (check_segmented_stable_sorted_device,
@@ -62,7 +64,7 @@ def test_1e8_invariants_on_device(name, pw):
     keys, idx = synth.make(name, n, payload_bytes=pw)
     base_k, base_p = dev(keys, idx)
     del keys, idx
-    cfg = zs.zsort_autotune(base_k, base_p)
+    cfg = bench.TUNED[name]
     say(f"case 1e8 {name} pw={pw} cfg={cfg}")
     tk, tp = base_k.clone(), base_p.clone()
     zs.zsort_stable_ex(tk, tp, cfg)

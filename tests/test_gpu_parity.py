@@ -381,3 +381,46 @@ def test_signed_flag_rejected_where_unsupported():
     with pytest.raises(zs.ZsortError) as ei:
         zs.zsort_debug_level0(tk, tp, dict(CFG, flags=zs.ZSORT_FLAG_SIGNED))
     assert ei.value.code == -5
+
+
+@pytest.mark.parametrize("cfg", [dict(k=256, cutoff=256, max_zlevels=8, chunk=4096, count_range=256),
+                                 dict(k=1024, cutoff=64, max_zlevels=8, chunk=2048, count_range=1000),
+                                 dict(k=4096, cutoff=2048, max_zlevels=8, chunk=32768,
+                                      count_range=4096)])
+def test_counting_pass_trace_parity(cfg):
+    """Counting-sort termination (small key ranges, Section III's heuristic):
+    the same subproblems take a counting pass (record kind 4) as in the oracle's
+    counting_range mode, every record agrees, the output is the oracle's, and
+    the recursion is no deeper than without the counting pass."""
+    for name in ["small_range", "clustered_ranges", "dup_heavy", "zipf"]:
+        n = 200_003
+        x, idx = synth.make(name, n)
+        say(f"case counting {name} {cfg}")
+        tk, tp = to_dev(x, idx)
+        rec, hist = zs.zsort_stable_traced(tk, tp, cfg)
+        k, p = from_dev(tk, tp)
+        ok, oi, info, otr, ohist = oracle.sort(
+            x, idx, k=cfg["k"], cutoff=cfg["cutoff"], max_zlevels=cfg["max_zlevels"],
+            counting_range=cfg["count_range"], trace=True)
+        assert np.array_equal(k, ok) and np.array_equal(p, oi)
+        assert len(rec) == len(otr) == info[0]
+        g = {(int(r["depth"]), int(r["start"])): r for r in rec}
+        for r in otr:
+            q = g[(int(r["depth"]), int(r["start"]))]
+            for f in ["kind", "count", "o", "M", "shift"]:
+                assert q[f] == r[f], (f, r, q)
+            assert np.array_equal(q["s1"], r["s1"]) and np.array_equal(q["s2"], r["s2"])
+        counted = int(np.count_nonzero(otr["kind"] == oracle.KIND_COUNT))
+        if name in ("small_range", "clustered_ranges"):
+            assert counted > 0
+        # the same sort through the plain entry point: stats and depth
+        tk, tp = to_dev(x, idx)
+        zs.zsort_stable_ex(tk, tp, cfg)
+        torch.cuda.synchronize()
+        st = zs.zsort_get_last_stats()
+        assert st["device_error"] == 0 and st["counted"] == counted
+        assert np.array_equal(from_dev(tk, tp)[0], ok)
+        tk, tp = to_dev(x, idx)
+        zs.zsort_stable_ex(tk, tp, dict(cfg, count_range=0))
+        torch.cuda.synchronize()
+        assert zs.zsort_get_last_stats()["levels"] >= st["levels"]

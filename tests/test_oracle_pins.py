@@ -414,3 +414,58 @@ def test_device_checkers_reject_planted_mistakes_on_cpu_tensors():
     check_segmented_stable_sorted_device(kin, sk, si, off)
     with pytest.raises(AssertionError):   # sorted as one array is not per segment
         check_segmented_stable_sorted_device(kin, kout, iout, off)
+
+
+# ---------------------------------------------------------------------------
+# 128-bit keys: the oracle's definition against brute force and a library sort
+# ---------------------------------------------------------------------------
+ALPHA128 = [(0, 0), (1, 0), (0, 1), (2**64 - 1, 0), (0, 2**64 - 1), (2**64 - 1, 2**64 - 1),
+            (5, 2**63), (5, 2**63 - 1)]
+
+
+def _brute128(keys, signed):
+    """selection of the least remaining key, first occurrence on ties"""
+    def val(k):
+        hi = int(k[1]) ^ (1 << 63) if signed else int(k[1])
+        return (hi << 64) | int(k[0])
+    rest = list(range(len(keys)))
+    out = []
+    while rest:
+        best = min(rest, key=lambda i: (val(keys[i]), i))
+        out.append(best)
+        rest.remove(best)
+    return out
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_sort128_exhaustive_tiny_vs_brute_force(signed):
+    import itertools
+    for combo in itertools.product(range(len(ALPHA128)), repeat=3):
+        keys = np.array([ALPHA128[c] for c in combo], dtype=np.uint64)
+        idx = np.arange(3, dtype=np.uint32)
+        k, p = oracle.sort128(keys, idx, signed=signed)
+        order = _brute128(keys, signed)
+        assert p.tolist() == order
+        assert np.array_equal(k, keys[order])
+
+
+def test_sort128_random_vs_lexsort_and_structure():
+    rng = np.random.default_rng(9)
+    for n in (0, 1, 2, 17, 1000, 4097):
+        hi = rng.integers(0, 4, size=n).astype(np.uint64) * np.uint64(2**62)
+        lo = rng.integers(0, 5, size=n).astype(np.uint64) * np.uint64(2**61)
+        keys = np.stack([lo, hi], axis=1)
+        idx = np.arange(n, dtype=np.uint32)
+        k, p = oracle.sort128(keys, idx)
+        order = np.lexsort((lo, hi))          # stable, last key primary
+        assert np.array_equal(p, order.astype(np.uint32))
+        assert np.array_equal(k, keys[order])
+        # signed: the high word's sign bit decides first
+        ks, ps = oracle.sort128(keys, idx, signed=True)
+        order_s = np.lexsort((lo, hi ^ np.uint64(2**63)))
+        assert np.array_equal(ps, order_s.astype(np.uint32))
+    # keys that differ only in the low word order as 64-bit keys do
+    lo = rng.integers(0, 2**64, size=3000, dtype=np.uint64)
+    keys = np.stack([lo, np.full(3000, 7, dtype=np.uint64)], axis=1)
+    k, p = oracle.sort128(keys, np.arange(3000, dtype=np.uint32))
+    assert np.array_equal(k[:, 0], np.sort(lo, kind="stable"))
