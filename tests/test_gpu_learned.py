@@ -318,3 +318,36 @@ def test_reused_parameters_reproduce_the_first_pass(mix):
     assert np.array_equal(tp.cpu().numpy().view(np.uint32), first[1])
     ek, ei, _ = oracle.sort(keys, idx, k=1024, cutoff=2048, max_zlevels=8)
     assert np.array_equal(first[0], ek) and np.array_equal(first[1], ei)
+
+
+@pytest.mark.parametrize("wl", ["gmm", "gmm_identity"])
+def test_training_against_initialisation_on_the_mixtures(wl):
+    """What the Adam steps add over the initialisation on the mixture shapes:
+    the sample's largest cluster under each parameter set, the rule that keeps
+    the trained parameters only when that cluster does not grow, and the
+    first-pass imbalance that results.  The numbers are printed; the test pins
+    the rule and the output, not which set wins."""
+    n = 1 << 24
+    keys, pay = synth.make(wl, n)
+    ek, ep, _ = oracle.sort(keys, pay, k=1024, cutoff=2048, max_zlevels=8)
+    base = dict(buckets=4096, flags=zs.ZSORT_LEARNED_ZSCORE_DIAG)
+    ok, op, r0, _ = learned_sort(keys, pay, CFG, dict(base, steps=0))
+    assert np.array_equal(ok, ek) and np.array_equal(op, ep)
+    assert r0["trained"] == 0 and r0["steps"] == 0
+    say(f"case training {wl}: init only: imbalance {r0['imbalance_learned']:.2f} "
+        f"(z-score {r0['imbalance_zscore']:.1f})")
+    init_max = None
+    for steps, lr in [(16, 1e-4), (64, 1e-3)]:
+        ok, op, r, _ = learned_sort(keys, pay, CFG, dict(base, steps=steps, lr=lr))
+        assert np.array_equal(ok, ek) and np.array_equal(op, ep)
+        assert r["steps"] == steps
+        # the initial parameters are the same in every call (same sample)
+        assert init_max is None or r["sample_max_init"] == init_max
+        init_max = r["sample_max_init"]
+        kept = r["sample_max_trained"] <= r["sample_max_init"]
+        assert r["trained"] == (1 if kept else 0)
+        if not kept:   # the initial parameters stay: the same first pass
+            assert r["max_cluster_learned"] == r0["max_cluster_learned"]
+        say(f"  {steps} steps lr {lr}: sample max {r['sample_max_trained']} "
+            f"(init {r['sample_max_init']}), kept {r['trained']}, imbalance "
+            f"{r['imbalance_learned']:.2f}, loss {r['loss_first']:.3g} -> {r['loss_last']:.3g}")
