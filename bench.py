@@ -377,7 +377,7 @@ def run_learned(steps, warmup, dev, n=10**8):
     keys, pay = synth.make("gmm", n, payload_bytes=4)
     base_k, base_p = to_device(keys, pay, dev)
     del keys, pay
-    cfg = zs.zsort_autotune(base_k, base_p)
+    cfg = TUNED["gmm"]   # the z-score line's configuration, for a like-for-like comparison
     par = torch.empty(zs.MLP_PARAMS_BYTES, dtype=torch.uint8, device=dev)
     k, p = base_k.clone(), base_p.clone()
     diag = zs.zsort_stable_learned(k, p, cfg, dict(flags=zs.ZSORT_LEARNED_ZSCORE_DIAG),
@@ -403,6 +403,7 @@ def run_learned(steps, warmup, dev, n=10**8):
         return ev0.elapsed_time(ev1) / steps, reps
 
     ms_fit, reps = timed(None)
+    ms_train, reps_t = timed(dict(steps=16))   # the initialisation refined by 16 Adam steps
     ms_reuse, reps2 = timed(reuse)
     st = zs.zsort_get_last_stats()
     ms_512, reps3 = timed(dict(reuse, buckets=512))
@@ -420,12 +421,15 @@ def run_learned(steps, warmup, dev, n=10**8):
             "first_pass_ms": round(sum(r["first_pass_ms"] for r in reps2) / len(reps2), 4),
             "imbalance_learned": round(diag["imbalance_learned"], 3),
             "imbalance_zscore": round(diag["imbalance_zscore"], 3),
-            "used_learned": sum(r["used_learned"] for r in reps + reps2 + reps3),
-            "fallbacks": sum(r["fallback"] for r in reps + reps2 + reps3),
-            "trained_kept": sum(r["trained"] for r in reps),
-            "sample_max_cluster_init_vs_trained": [reps[0]["sample_max_init"],
-                                                   reps[0]["sample_max_trained"]],
-            "levels": st["levels"], "calls": len(reps) + len(reps2) + len(reps3)}
+            "used_learned": sum(r["used_learned"] for r in reps + reps_t + reps2 + reps3),
+            "fallbacks": sum(r["fallback"] for r in reps + reps_t + reps2 + reps3),
+            "adam_steps": reps[0]["steps"],
+            "ms_per_step_with_16_adam_steps": round(ms_train, 4),
+            "fit_ms_with_16_adam_steps": round(sum(r["train_ms"] for r in reps_t) / len(reps_t), 4),
+            "trained_kept_of_16_step_fits": f"{sum(r['trained'] for r in reps_t)}/{len(reps_t)}",
+            "sample_max_cluster_init_vs_trained": [reps_t[0]["sample_max_init"],
+                                                   reps_t[0]["sample_max_trained"]],
+            "levels": st["levels"], "calls": len(reps) + len(reps_t) + len(reps2) + len(reps3)}
 
 
 def roofline(kt, stats, pw, steps, traffic_file, cfg):

@@ -441,7 +441,9 @@ typedef struct zsort_mlp_params {
 typedef struct zsort_learned_config {
   int32_t buckets;        /* B: clusters of the first pass, 16..4096; default 4096 */
   int32_t sample_stride;  /* one key per stride is sampled; default 100 (1 %) */
-  int32_t steps;          /* Adam steps, 0 = initialisation only; default 16 */
+  int32_t steps;          /* Adam steps, 0 = initialisation only (default: on the
+                             mixture shapes no step count lowered the sample's
+                             largest cluster, so the initialisation was kept anyway) */
   int32_t batches;        /* step t uses samples i with i mod batches == t mod batches; default 64 */
   double lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8); default 1e-4 */
   uint64_t seed;          /* sample offsets */

@@ -2136,7 +2136,7 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
 // more than 51 bits or some bucket holds more than kBucketMax keys; such
 // groups go to the fallback sort.
 // ---------------------------------------------------------------------------
-constexpr int kBucketMax = 16;
+constexpr int kBucketMax = 128;
 
 constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2); }
 

@@ -402,17 +402,20 @@ __global__ void __launch_bounds__(64) k_lreduce(const float* __restrict__ part, 
 
 // ---------------------------------------------------------------------------
 // thresholds: t_b = min{x : cluster(x) >= b}, b = 1..nt, nt = cluster(2^64 - 1).
-// A 17-way search: 16 lanes evaluate 16 points that cut [lo, hi] into 17
-// parts, the first point whose cluster is >= b bounds the next interval;
-// about 16 rounds instead of 64 bisection steps.  For a non-decreasing map
-// the least such key is unique, so any exact search finds the same t_b.
+// A 65-way search by one wave per threshold: its 64 lanes evaluate 64 points
+// that cut [lo, hi] into 65 parts, and the first point whose cluster is >= b
+// bounds the next interval -- about 11 rounds instead of 64 bisection steps,
+// with a wave per threshold so that the LDS reads of the weights overlap
+// across many waves.  For a non-decreasing map the least such key is unique,
+// so any exact search finds the same t_b.
 // ---------------------------------------------------------------------------
-constexpr int kTLanes = 16;
+constexpr int kTLanes = kWave;
+constexpr uint64_t kTParts = kTLanes + 1;
 
 __device__ __forceinline__ uint64_t tpoint(uint64_t lo, uint64_t d, uint32_t j) {
-  // lo + floor(d * j / 17) without 128-bit arithmetic (j <= 16)
-  const uint64_t q = d / 17, r = d % 17;
-  return lo + q * j + (r * j) / 17;
+  // lo + floor(d * j / 65) without 128-bit arithmetic (j <= 64)
+  const uint64_t q = d / kTParts, r = d % kTParts;
+  return lo + q * j + (r * j) / kTParts;
 }
 
 __global__ void __launch_bounds__(256) k_lthresh(const MlpP* __restrict__ par, int B, LRes* res,
@@ -423,33 +426,29 @@ __global__ void __launch_bounds__(256) k_lthresh(const MlpP* __restrict__ par, i
   const uint64_t smin = res->smin, smax = res->smax;
   const uint32_t nt = mlp_cluster(sp, ~0ull, smin, smax, B);
   if (blockIdx.x == 0 && threadIdx.x == 0) res->nt = nt;
-  const uint32_t ln = threadIdx.x & (kWave - 1);
-  const uint32_t grp = ln / kTLanes, j = ln % kTLanes + 1;   // point j of 1..16
-  const uint32_t per_wave = kWave / kTLanes;
+  const uint32_t j = (threadIdx.x & (kWave - 1)) + 1;   // point j of 1..64
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
-  for (uint32_t base = wid * per_wave; base < (uint32_t)B - 1; base += nwaves * per_wave) {
-    const uint32_t b = base + grp + 1;            // this group's threshold
-    bool active = b <= nt;
+  for (uint32_t b = wid + 1; b < (uint32_t)B; b += nwaves) {   // this wave's threshold
+    if (b > nt) {
+      if (j == 1) thr[b - 1] = 0;
+      continue;
+    }
     uint64_t lo = 0, hi = ~0ull;                  // the answer lies in [lo, hi]
-    while (__ballot(active)) {
+    while (lo < hi) {
       const uint64_t d = hi - lo;
       const uint64_t p = tpoint(lo, d, j);
-      const bool pred = active && mlp_cluster(sp, p, smin, smax, B) >= b;
-      const uint32_t mask = (uint32_t)(__ballot(pred) >> (grp * kTLanes)) & 0xFFFFu;
-      if (active) {
-        if (mask) {
-          const uint32_t js = __ffs(mask);        // first point (1-based) with cluster >= b
-          const uint64_t nhi = tpoint(lo, d, js);
-          if (js > 1) lo = tpoint(lo, d, js - 1) + 1;
-          hi = nhi;
-        } else {
-          lo = tpoint(lo, d, kTLanes) + 1;
-        }
-        if (lo >= hi) active = false;
+      const uint64_t mask = __ballot(mlp_cluster(sp, p, smin, smax, B) >= b);
+      if (mask) {
+        const uint32_t js = (uint32_t)__ffsll((unsigned long long)mask);   // first point (1-based)
+        const uint64_t nhi = tpoint(lo, d, js);
+        if (js > 1) lo = tpoint(lo, d, js - 1) + 1;
+        hi = nhi;
+      } else {
+        lo = tpoint(lo, d, kTLanes) + 1;
       }
     }
-    if (j == 1 && b < (uint32_t)B) thr[b - 1] = b <= nt ? lo : 0;
+    if (j == 1) thr[b - 1] = lo;
   }
 }
 
@@ -757,7 +756,7 @@ hipError_t launch_ltrain(const double* U, const float* Y, uint64_t m, uint32_t n
 }
 
 hipError_t launch_lthresh(const MlpP* par, int B, LRes* res, uint64_t* thr, hipStream_t st) {
-  const int blocks = ((B - 1) * kTLanes + 255) / 256;
+  const int blocks = ((B - 1) * kTLanes + 255) / 256;   // a wave per threshold
   hipLaunchKernelGGL(k_lthresh, dim3(std::max(blocks, 1)), dim3(256), 0, st, par, B, res, thr);
   return hipGetLastError();
 }

@@ -203,7 +203,7 @@ CFG = dict(k=1024, cutoff=2048, max_zlevels=8, chunk=16384, tile=2048)
 def test_learned_sort_matches_oracle(wl, n, pw):
     keys, pay = synth.make(wl, n, payload_bytes=pw)
     say(f"case learned sort {wl} n={n} pw={pw}")
-    ok, op, rep, st = learned_sort(keys, pay, CFG, dict(buckets=4096))
+    ok, op, rep, st = learned_sort(keys, pay, CFG, dict(buckets=4096, steps=16))
     assert rep["used_learned"] == 1 and rep["fallback"] == 0, rep
     assert rep["steps"] == 16 and rep["thresholds"] > 0
     # the parameters with the smaller largest sample cluster are kept
