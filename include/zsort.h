@@ -207,18 +207,19 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
 /*
  * 128-bit keys (an extension named by the paper's motivation, Section I: the
  * number of distribution passes does not grow with the key width, unlike a
- * radix sort's).  keys: DEVICE array of n keys of 16 bytes, each the two u64
- * words of an unsigned 128-bit integer, low word first; sorted in place,
- * stably, with an optional u32 payload (may be NULL).  Two z-score stages
- * over 64-bit words: the high words of all keys are sorted (Algorithm 1,
- * Eq. (1)), each carrying its key's position; then every run of equal high
+ * radix sort's).  keys: DEVICE array of n keys of 16 bytes (16-byte aligned),
+ * each the two u64 words of an unsigned 128-bit integer, low word first;
+ * sorted in place, stably, with an optional u32 payload (may be NULL).  Two
+ * z-score stages over 64-bit words: the high words of all keys are sorted
+ * (Algorithm 1, Eq. (1)), each carrying its key's low word (or, with a
+ * payload, the payload and the key's position); then every run of equal high
  * words is sorted by its low words -- inside such a run the key rebased to
  * the run's minimum fits 64 bits.  Runs of at most 64 keys are sorted at
  * once by an insertion sort; longer ones by the same distribution as a batch
  * of subproblems.  ZSORT_FLAG_SIGNED orders the keys as two's-complement
- * int128; ZSORT_FLAG_GRAPH returns ZSORT_EUNSUPPORTED.  The stream keeps
- * buffers of 24 bytes per key for the stages (plus the workspace of the
- * 64-bit sort with a u32 payload).  report (host, may be NULL) makes the call
+ * int128; ZSORT_FLAG_GRAPH returns ZSORT_EUNSUPPORTED; a misaligned keys
+ * pointer ZSORT_EINVAL.  The stream keeps buffers of 16 bytes per key for the
+ * stages (plus the workspace of the 64-bit sort with an 8-byte payload).  report (host, may be NULL) makes the call
  * synchronous and receives the recursion depth of each stage and the runs.
  */
 typedef struct zsort_u128_report {

@@ -24,14 +24,11 @@ hipError_t scratch_address(int dev, void** out);
 hipError_t launch_init_runs(const Ws& ws, const uint32_t* runs, const uint32_t* nruns, int grid,
                             hipStream_t st);
 hipError_t launch_split128(const uint64_t* keys, const uint32_t* payload, uint64_t n, int sgn,
-                           uint64_t* hi, uint32_t* idx, uint32_t* pay_copy, uint32_t* nruns,
-                           int grid, hipStream_t st);
-hipError_t launch_gather_runs(const uint64_t* keys, const uint64_t* hi, uint32_t* idx, uint64_t n,
-                              uint64_t* lo, uint32_t* runs, uint32_t* nruns, int grid,
-                              hipStream_t st);
-hipError_t launch_final128(uint64_t* keys, uint32_t* payload, uint64_t n, int sgn,
-                           const uint64_t* hi, const uint64_t* lo, const uint32_t* idx,
-                           const uint32_t* pay_copy, int grid, hipStream_t st);
+                           uint64_t* hi, uint64_t* second, uint32_t* nruns, hipStream_t st);
+hipError_t launch_gather_runs(const uint64_t* keys, const uint64_t* hi, uint64_t n, uint64_t* lo,
+                              uint32_t* payload, uint32_t* runs, uint32_t* nruns, hipStream_t st);
+hipError_t launch_final128(uint64_t* keys, uint64_t n, int sgn, const uint64_t* hi,
+                           const uint64_t* lo, hipStream_t st);
 hipError_t launch_check_sorted(const uint64_t* keys, uint64_t n, uint32_t* flag, int grid,
                                hipStream_t st);
 hipError_t launch_flip(uint64_t* keys, uint64_t n, int grid, hipStream_t st);
@@ -91,7 +88,7 @@ struct Shape {
 
 struct Layout {
   size_t off_ctl, off_keys, off_pay, off_segs[2], off_work[2], off_leaves[2], off_leavesw[2],
-      off_leavesm[2],
+      off_leavesm[2], off_leavesx[2],
       off_hard[2],
       off_status, off_arrive[2], off_part,
       off_bstart, off_subpre, off_tiles[2], off_trace, off_thist, total;
@@ -137,6 +134,7 @@ Layout plan(const Shape& s) {
     L.off_leaves[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_leavesw[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_leavesm[i] = take(leaf_cap * sizeof(zs::Leaf));
+    L.off_leavesx[i] = take(leaf_cap * sizeof(zs::Leaf));
     L.off_hard[i] = take(leaf_cap * sizeof(zs::Leaf));
   }
   // scan rows [row][k]; a learned first pass has one root of nchunks work
@@ -358,6 +356,7 @@ Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay
     ws.leaves[i] = (zs::Leaf*)(base + L.off_leaves[i]);
     ws.leavesw[i] = (zs::Leaf*)(base + L.off_leavesw[i]);
     ws.leavesm[i] = (zs::Leaf*)(base + L.off_leavesm[i]);
+    ws.leavesx[i] = (zs::Leaf*)(base + L.off_leavesx[i]);
     ws.hard[i] = (zs::Leaf*)(base + L.off_hard[i]);
   }
   ws.status = (uint64_t*)(base + L.off_status);
@@ -879,9 +878,7 @@ struct WideWs {
   char* base = nullptr;
   uint64_t n_cap = 0;
   uint64_t* hi = nullptr;
-  uint64_t* lo = nullptr;
-  uint32_t* idx = nullptr;
-  uint32_t* pay = nullptr;
+  uint64_t* lo = nullptr;   // first the word the high words carry, then the low words
   uint32_t* runs = nullptr;
   uint32_t* counters = nullptr;  // [0] runs, [2..3] keys in runs (u64)
 };
@@ -902,8 +899,7 @@ int wide_acquire(hipStream_t st, uint64_t n, WideWs** out) {
     return at;
   };
   const uint64_t nr = n / 65 + 1;   // runs of > 64 keys
-  const size_t o_hi = take(n * 8), o_lo = take(n * 8), o_idx = take(n * 4), o_pay = take(n * 4),
-               o_runs = take(nr * 8), o_cnt = take(16);
+  const size_t o_hi = take(n * 8), o_lo = take(n * 8), o_runs = take(nr * 8), o_cnt = take(16);
   if (w->base) {
     hipError_t e = hipFree(w->base);
     w->base = nullptr;
@@ -918,8 +914,6 @@ int wide_acquire(hipStream_t st, uint64_t n, WideWs** out) {
   w->n_cap = n;
   w->hi = (uint64_t*)(b + o_hi);
   w->lo = (uint64_t*)(b + o_lo);
-  w->idx = (uint32_t*)(b + o_idx);
-  w->pay = (uint32_t*)(b + o_pay);
   w->runs = (uint32_t*)(b + o_runs);
   w->counters = (uint32_t*)(b + o_cnt);
   *out = w;
@@ -948,10 +942,10 @@ extern "C" {
 int zsort_stable_u128(uint64_t* keys, uint32_t* payload, size_t n, const zsort_config* cfg,
                       zsort_u128_report* report, void* stream) {
   if (report) std::memset(report, 0, sizeof *report);
-  if (n > 0x7FFFFFFFull || (n > 1 && !keys)) return ZSORT_EINVAL;
+  if (n > 0x7FFFFFFFull || (n > 1 && !keys) || ((uintptr_t)keys & 15u)) return ZSORT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   zsort_config c;
-  int rc = resolve_cfg(cfg, &c, n, 4, 0);
+  int rc = resolve_cfg(cfg, &c, n, 8, 0);   // (the high words carry 8 bytes)
   if (rc) return rc;
   if (c.flags & ZSORT_FLAG_GRAPH) return ZSORT_EUNSUPPORTED;
   if (n <= 1) return ZSORT_OK;
@@ -961,19 +955,11 @@ int zsort_stable_u128(uint64_t* keys, uint32_t* payload, size_t n, const zsort_c
   WideWs* w = nullptr;
   rc = wide_acquire(st, n, &w);
   if (rc) return rc;
-  if (!g_cu_count) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-      e = hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  const int grid = std::max(1, g_cu_count) * 8;
-  // stage 1: the high words, each carrying its key's position
-  hipError_t e = zs::launch_split128(keys, payload, n, sgn, w->hi, w->idx, w->pay, w->counters,
-                                     grid, st);
+  // stage 1: the high words, each carrying its key's low word (no payload)
+  // or its payload and position (so that the payload needs no gather later)
+  hipError_t e = zs::launch_split128(keys, payload, n, sgn, w->hi, w->lo, w->counters, st);
   if (e != hipSuccess) return hip_fail(e);
-  Call hc{w->hi, w->idx, 4, (uint64_t)n, nullptr, 0, c, 0, 0, false};
+  Call hc{w->hi, w->lo, 8, (uint64_t)n, nullptr, 0, c, 0, 0, false};
   rc = run(hc, st, nullptr);
   if (rc) return rc;
   if (report) {
@@ -983,16 +969,17 @@ int zsort_stable_u128(uint64_t* keys, uint32_t* payload, size_t n, const zsort_c
     if (rc) return rc;
   }
   // stage 2: the low words inside every run of equal high words (the key
-  // rebased to the run's minimum fits 64 bits there)
-  e = zs::launch_gather_runs(keys, w->hi, w->idx, n, w->lo, w->runs, w->counters, grid, st);
+  // rebased to the run's minimum fits 64 bits there); the payload, unpacked
+  // into the caller's array, moves with them
+  e = zs::launch_gather_runs(keys, w->hi, n, w->lo, payload, w->runs, w->counters, st);
   if (e != hipSuccess) return hip_fail(e);
-  Call lc{w->lo, w->idx, 4, (uint64_t)n, nullptr, 0, c, 0, 0, false};
+  Call lc{w->lo, payload, payload ? 4 : 0, (uint64_t)n, nullptr, 0, c, 0, 0, false};
   lc.runs = w->runs;
   lc.nruns = w->counters;
   lc.runs_cap = (int64_t)(n / 65 + 1);
   rc = run(lc, st, nullptr);
   if (rc) return rc;
-  e = zs::launch_final128(keys, payload, n, sgn, w->hi, w->lo, w->idx, w->pay, grid, st);
+  e = zs::launch_final128(keys, n, sgn, w->hi, w->lo, st);
   if (e != hipSuccess) return hip_fail(e);
   if (report) {
     e = hipStreamSynchronize(st);

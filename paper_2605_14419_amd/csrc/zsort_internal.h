@@ -113,6 +113,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nleaf[2];             // block jobs: big leaves and copies
   uint32_t nleafw[2];            // wave jobs: groups of <= wave_job_cap(pw) keys
   uint32_t nleafm[2];            // one-wave jobs of wave_job_cap(pw) < n <= kMidCap keys
+  uint32_t nleafx[2];            // wave jobs (<= kWaveCap keys) that may span 2^51 keys
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
   uint32_t tick[kMaxLevels];     // work-item tickets of the hist pass
@@ -219,6 +220,7 @@ struct Ws {
   Leaf* leaves[2];       // block jobs
   Leaf* leavesw[2];      // wave jobs
   Leaf* leavesm[2];      // mid-size jobs (one wave, up to kMidCap keys)
+  Leaf* leavesx[2];      // wave jobs of a wide key range (the fallback kernel's first loop)
   Leaf* hard[2];         // jobs for the fallback local sort
   uint64_t* status;      // scan rows [row][k], tagged words: a work item's counts,
                          // turned into its inclusive prefix within its unit; then

@@ -210,17 +210,18 @@ __device__ void block_scan_multi(uint32_t* const (&a)[NA], int N, uint32_t (*sh)
 }
 
 // three exclusive sums of one value per thread at once
-__device__ __forceinline__ void block_excl_sum3(const uint32_t (&v)[3], uint32_t (*sh)[kWaves],
-                                                uint32_t (&ex)[3], uint32_t (&tot)[3]) {
-  uint32_t inc[3];
+template <int NA>
+__device__ __forceinline__ void block_excl_sums(const uint32_t (&v)[NA], uint32_t (*sh)[kWaves],
+                                                uint32_t (&ex)[NA], uint32_t (&tot)[NA]) {
+  uint32_t inc[NA];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < NA; ++q) {
     inc[q] = wave_incl_sum(v[q]);
     if (lane() == kWave - 1) sh[q][wave()] = inc[q];
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < NA; ++q) {
     uint32_t base = 0, t = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
@@ -435,18 +436,34 @@ __device__ __forceinline__ void for_each_key(const uint64_t* __restrict__ x, uin
   if (a1 <= a0) return;
   const ulonglong2* __restrict__ xp = reinterpret_cast<const ulonglong2*>(x + a0);
   const uint64_t np = (a1 - a0) >> 1;
-  for (uint64_t p = t; p < np; p += (uint64_t)kBlock * UNROLL) {
-    ulonglong2 v[UNROLL];
+  // two register sets: the next group of key pairs is loaded before the
+  // current one is visited, so that every wave keeps loads in flight
+  const uint64_t step = (uint64_t)kBlock * UNROLL;
+  ulonglong2 va[UNROLL], vb[UNROLL];
+  auto load = [&](ulonglong2 (&v)[UNROLL], uint64_t p) {
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const uint64_t q = p + (uint64_t)u * kBlock;
       if (q < np) v[u] = xp[q];
     }
+  };
+  auto visit = [&](const ulonglong2 (&v)[UNROLL], uint64_t p) {
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const uint64_t q = p + (uint64_t)u * kBlock;
       if (q < np) { f(a0 + 2 * q, v[u].x); f(a0 + 2 * q + 1, v[u].y); }
     }
+  };
+  uint64_t p = t;
+  if (p < np) load(va, p);
+  while (p < np) {
+    if (p + step < np) load(vb, p + step);
+    visit(va, p);
+    p += step;
+    if (p >= np) break;
+    if (p + step < np) load(va, p + step);
+    visit(vb, p);
+    p += step;
   }
 }
 
@@ -528,7 +545,8 @@ __global__ void k_reset(Ws ws) {
     c->clear_rows = clr ? 1u : 0u;
     if (clr) c->clear_epoch = ep;
     for (int s = 0; s < 2; ++s) {
-      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nleafm[s] = 0; c->nhard[s] = 0;
+      c->nseg[s] = 0; c->nwork[s] = 0; c->nleaf[s] = 0; c->nleafw[s] = 0; c->nleafm[s] = 0;
+      c->nleafx[s] = 0; c->nhard[s] = 0;
       c->nstatus[s] = 0; c->ntile[s] = 0;
     }
     c->error = 0;
@@ -656,6 +674,7 @@ __global__ void k_reset_lists(Ws ws, int slot) {
   Ctl* c = ws.ctl;
   if (threadIdx.x == 0) {
     c->nseg[slot] = 0; c->nwork[slot] = 0; c->nleaf[slot] = 0; c->nleafw[slot] = 0; c->nleafm[slot] = 0;
+    c->nleafx[slot] = 0;
     c->nhard[slot] = 0; c->nstatus[slot] = 0; c->ntile[slot] = 0;
   }
 }
@@ -742,12 +761,52 @@ __global__ void k_init_segments(Ws ws, const int64_t* off, int32_t nseg) {
     init_root(ws, (uint64_t)off[i], (uint64_t)(off[i + 1] - off[i]));
 }
 
-// subproblems given as (start, length) pairs, *nruns of them (device count)
+// subproblems given as (start, length) pairs, *nruns of them (device count):
+// a workgroup per run, whose thread 0 makes the segment (or the leaf) and
+// whose threads then write its work items and tiles (a run may be the whole
+// array: thousands of entries)
 __global__ void k_init_runs(Ws ws, const uint32_t* runs, const uint32_t* nruns) {
   clear_rows_if_due(ws);
+  Ctl* c = ws.ctl;
+  __shared__ uint32_t sh[5];   // segment, first work item, chunks, first tile, tiles
   const uint32_t nr = *nruns;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x)
-    init_root(ws, runs[2 * i], runs[2 * i + 1]);
+  const uint64_t ch = (uint64_t)ws.p.chunk;
+  const uint32_t nsub = tiles_per_item(ws);
+  const int t = threadIdx.x;
+  for (uint32_t i = blockIdx.x; i < nr; i += gridDim.x) {
+    const uint64_t a = runs[2 * i], len = runs[2 * i + 1];
+    if (t == 0) {
+      sh[2] = 0u;   // nothing to write unless a segment is made
+      if (len > (uint64_t)ws.p.cutoff) {
+        const uint32_t nch = (uint32_t)((len + ch - 1) / ch);
+        const uint32_t ntl = nsub > 1 ? (uint32_t)((len + 8191) >> 13) : 0u;
+        const uint32_t si = atomicAdd(&c->nseg[0], 1u);
+        const uint32_t wi = atomicAdd(&c->nwork[0], nch);
+        const uint32_t sb = nch > 1 ? atomicAdd(&c->nstatus[0], status_rows(nch)) : 0u;
+        const uint32_t ti = ntl ? atomicAdd(&c->ntile[0], ntl) : 0u;
+        if (si >= ws.seg_cap || wi + nch > ws.work_cap || sb + status_rows(nch) > ws.status_cap) {
+          atomicOr(&c->error, ERR_SEGCAP);
+        } else if (ntl && ti + ntl > ws.tile_cap) {
+          atomicOr(&c->error, ERR_WORKCAP);
+        } else {
+          make_root_seg(ws, si, a, len, wi, nch, sb);
+          clear_arrivals(ws.arrive[0] + sb, nch);
+          sh[0] = si; sh[1] = wi; sh[2] = nch; sh[3] = ti; sh[4] = ntl;
+        }
+      } else if (len > 1) {
+        push_leaf(ws, 0, a, (uint32_t)len, 0u, 0u);
+        atomicAdd(&c->n_leafgroups, 1u);
+      }
+    }
+    __syncthreads();
+    const uint32_t nch = sh[2];
+    if (nch) {
+      const uint64_t segw = (uint64_t)sh[0] << 32;
+      for (uint32_t j = t; j < nch; j += blockDim.x) ws.work[0][sh[1] + j] = segw | j;
+      for (uint32_t u = t; u < sh[4]; u += blockDim.x) ws.tiles[0][sh[3] + u] = tile_entry(sh[0], u, nsub);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -876,7 +935,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   const int S = L & 1, N = S ^ 1;
   if (call_failed(c)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
-    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nleafm[N] = 0; c->nhard[N] = 0;
+    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nleafm[N] = 0;
+    c->nleafx[N] = 0; c->nhard[N] = 0;
     c->nstatus[N] = 0; c->ntile[N] = 0;
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
@@ -1044,12 +1104,54 @@ struct alignas(16) HistSmem {   // t0, t1 double as KMAX 64-bit words (learned t
   uint32_t shm[5][kWaves];  // wave totals of the multi-array scans
   uint32_t w;
   uint32_t last;          // this workgroup arrived last at a scan unit / segment
-  uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid;
+  uint32_t base_seg, base_work, base_status, base_leaf, base_tile, base_mid, base_wide;
   // statistics of this workgroup's segments, added to the control block at
   // the end of the kernel
   unsigned long long st_keys;
   uint32_t st_segs, st_groups;
 };
+
+// Which leaf groups of a distributed segment may span 2^51 keys or more, in
+// whole clusters: a group of clusters b0..b1 counts b1 - b0 + 1 clusters,
+// plus x0 more if it holds the clipped first cluster and x1 if it holds the
+// clipped last one (those reach the segment's extremes), and is wide when the
+// count reaches nwide.  Computed once per segment from the map: an interior
+// cluster spans 1/A keys (z-map), 2^shift (range map), 1 (counting pass).
+// Only routes groups between local sorts; rounding here changes no result.
+struct WideRule {
+  uint32_t nwide, x0, x1;
+};
+__device__ WideRule wide_rule(const Seg& s, int k) {
+  WideRule w{0xFFFFFFFFu, 0u, 0u};
+  const double full = __ull2double_rn(s.M - s.o);
+  if (!(full >= 0x1p51) || s.kind == KIND_COUNT) return w;
+  auto clusters = [](double x) {   // a width in whole clusters, clamped
+    return !(x < 0x1p31) ? 0x80000000u : (x > 0.0 ? (uint32_t)x : 0u);
+  };
+  if (s.kind == KIND_RMAP) {
+    w.nwide = s.shift >= 51 ? 1u : (1u << min(51 - s.shift, 31));
+  } else if (s.kind == KIND_ZMAP && s.A > 0.0) {
+    w.nwide = max(clusters(0x1p51 * s.A), 1u);
+    w.x0 = clusters((s.m + (1.0 - s.B) / s.A) * s.A);
+    w.x1 = clusters((full - (s.m + ((double)(k - 1) - s.B) / s.A)) * s.A);
+  } else {
+    w.nwide = 1u;   // a learned map: any group of such a segment may be wide
+  }
+  return w;
+}
+
+// the cluster holding position p of a distributed segment: the last one
+// starting at or before p (a non-empty one when p < the segment's count)
+template <int KMAX>
+__device__ __forceinline__ int cluster_at(const HistSmem<KMAX>& sm, int k, uint32_t p) {
+  int lo = 0, hi = k - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sm.bst[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 template <int KMAX>
 __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L) {
@@ -1272,44 +1374,61 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       if (sm.t1[b]) bpos[sm.t2[b]] = sm.bst[b] | (sm.t1[b] == 2 ? 0x80000000u : 0u);
     __syncthreads();
     const uint32_t wcap = (uint32_t)wave_job_cap(ws.p.pw);
-    uint32_t my_small = 0, my_mid = 0, my_big = 0;
+    // A wave-sized group whose keys may span 2^51 or more goes to the wide
+    // list: the fast local sort's words cannot hold such a range next to the
+    // position, and the fallback kernel's first loop takes these groups
+    // without a failed attempt first (only a segment that wide can have them).
+    const WideRule wr = wide_rule(sg, k);
+    auto is_wide = [&](uint32_t p0, uint32_t p1) {
+      if (wr.nwide == 0xFFFFFFFFu || p1 - p0 > (uint32_t)kWaveCap) return false;
+      const int b0 = cluster_at(sm, k, p0), b1 = cluster_at(sm, k, p1 - 1);
+      const uint64_t nc = (uint64_t)(b1 - b0 + 1) + (b0 == 0 ? wr.x0 : 0u) +
+                          (b1 == k - 1 ? wr.x1 : 0u);
+      return nc >= wr.nwide;
+    };
+    uint32_t my_small = 0, my_mid = 0, my_big = 0, my_wide = 0;
     for (uint32_t i = t; i < nb; i += kBlock) {
       if (!(bpos[i] >> 31)) continue;
       const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
       const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
-      if (p1 - p0 <= wcap) ++my_small;
+      if (is_wide(p0, p1)) ++my_wide;
+      else if (p1 - p0 <= wcap) ++my_small;
       else if (p1 - p0 <= (uint32_t)kMidCap) ++my_mid;
       else ++my_big;
     }
-    const uint32_t mine[3] = {my_small, my_mid, my_big};
-    uint32_t offs[3], tots[3];
-    block_excl_sum3(mine, sm.shm, offs, tots);
-    const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2];
-    const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2];
-    // the three leaf lists, likewise in one atomic instruction
-    if (t < 3) {
-      uint32_t* ctr = t == 0 ? &c->nleafw[S] : (t == 1 ? &c->nleafm[S] : &c->nleaf[S]);
-      const uint32_t v = t == 0 ? nsmall : (t == 1 ? nmid : nbig);
+    const uint32_t mine[4] = {my_small, my_mid, my_big, my_wide};
+    uint32_t offs[4], tots[4];
+    block_excl_sums<4>(mine, sm.shm, offs, tots);
+    const uint32_t off_small = offs[0], off_mid = offs[1], off_big = offs[2], off_wide = offs[3];
+    const uint32_t nsmall = tots[0], nmid = tots[1], nbig = tots[2], nwide = tots[3];
+    // the four leaf lists, likewise in one atomic instruction
+    if (t < 4) {
+      uint32_t* ctr = t == 0 ? &c->nleafw[S]
+                    : (t == 1 ? &c->nleafm[S] : (t == 2 ? &c->nleaf[S] : &c->nleafx[S]));
+      const uint32_t v = t == 0 ? nsmall : (t == 1 ? nmid : (t == 2 ? nbig : nwide));
       const uint32_t r = v ? atomicAdd(ctr, v) : 0u;
       // (base_status is reused as the big-list base)
-      uint32_t* out = t == 0 ? &sm.base_leaf : (t == 1 ? &sm.base_mid : &sm.base_status);
+      uint32_t* out = t == 0 ? &sm.base_leaf
+                    : (t == 1 ? &sm.base_mid : (t == 2 ? &sm.base_status : &sm.base_wide));
       *out = r;
     }
-    if (t == 0) sm.st_groups += nsmall + nmid + nbig;
+    if (t == 0) sm.st_groups += nsmall + nmid + nbig + nwide;
     __syncthreads();
-    if (t == 0 && (sm.base_leaf + nsmall > ws.leaf_cap || sm.base_mid + nmid > ws.leaf_cap ||
-                   sm.base_status + nbig > ws.leaf_cap))
-      atomicOr(&c->error, ERR_LEAFCAP);
-    if (sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
-        sm.base_status + nbig <= ws.leaf_cap) {
+    const bool fits = sm.base_leaf + nsmall <= ws.leaf_cap && sm.base_mid + nmid <= ws.leaf_cap &&
+                      sm.base_status + nbig <= ws.leaf_cap && sm.base_wide + nwide <= ws.leaf_cap;
+    if (t == 0 && !fits) atomicOr(&c->error, ERR_LEAFCAP);
+    if (fits) {
       uint32_t os = sm.base_leaf + off_small, om = sm.base_mid + off_mid, ob = sm.base_status + off_big;
+      uint32_t ox = sm.base_wide + off_wide;
       for (uint32_t i = t; i < nb; i += kBlock) {
         if (!(bpos[i] >> 31)) continue;
         const uint32_t p0 = bpos[i] & 0x7FFFFFFFu;
         const uint32_t p1 = (i + 1 < nb) ? (bpos[i + 1] & 0x7FFFFFFFu) : (uint32_t)sg_count;
-        const bool small = p1 - p0 <= wcap;
-        const bool mid = !small && p1 - p0 <= (uint32_t)kMidCap;
-        Leaf& lf = small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]);
+        const bool wide = is_wide(p0, p1);
+        const bool small = !wide && p1 - p0 <= wcap;
+        const bool mid = !wide && !small && p1 - p0 <= (uint32_t)kMidCap;
+        Leaf& lf = wide ? ws.leavesx[S][ox++]
+                 : (small ? ws.leavesw[S][os++] : (mid ? ws.leavesm[S][om++] : ws.leaves[S][ob++]));
         lf.start = (uint32_t)(sg_start + p0);
         lf.count = p1 - p0;
         lf.flags = 0;
@@ -1886,8 +2005,9 @@ template <int PW>
 struct LocSmem {
   uint64_t k[kLocalCap + kLocalCap / 16];   // packed words (padded) / radix staging
   typename PayT<PW>::T pay[PW ? kLocalCap : 1];
-  uint32_t cnt[kWaves][256];
-  uint32_t tot[kWaves][256];
+  // radix counters (rows 0 .. kWaves-1) and totals (the other rows); the
+  // bucket sort's 16-bit counters span the whole array
+  uint32_t cnt[2 * kWaves][256];
   uint64_t rmin[kWaves], rmax[kWaves];
   uint32_t sh[kWaves + 2];
 };
@@ -1911,16 +2031,224 @@ __device__ __forceinline__ void team_scan256(uint32_t* a, uint32_t* sh, uint32_t
   }
 }
 
+constexpr int kBucketMax = 128;
+
+constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2); }
+
+__device__ __forceinline__ uint32_t c16_get(const uint32_t* c, uint32_t b) {
+  return (c[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
+}
+
+// Turns the nb 16-bit bucket counters (two per word) into exclusive starts;
+// returns false, leaving the counters as they are, if some bucket holds more
+// than kBucketMax keys.  Each thread owns ceil(nb / TT) consecutive counters.
+template <int TW>
+__device__ __forceinline__ bool bucket_starts(uint32_t* cnt, uint32_t nb, uint32_t* sh,
+                                              uint32_t tid) {
+  constexpr uint32_t TT = TW * kWave;
+  const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
+  const uint32_t per = (nb + TT - 1) / TT;
+  const uint32_t b0 = tid * per;
+  uint32_t tsum = 0, tmax = 0;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint32_t b = b0 + j;
+    if (b < nb) {
+      const uint32_t v = c16_get(cnt, b);
+      tsum += v;
+      tmax = v > tmax ? v : tmax;
+    }
+  }
+  uint32_t base;
+  uint32_t big = __ballot(tmax > (uint32_t)kBucketMax) != 0ull ? 1u : 0u;
+  if constexpr (TW == 1) {
+    base = wave_incl_sum(tsum) - tsum;
+  } else {
+    if (ln == 0) sh[tw] = big;
+    team_sync<TW>();
+    for (int q = 0; q < TW; ++q) big |= sh[q];
+    team_sync<TW>();
+    uint32_t total;
+    base = block_excl_sum<TW * kWave>(tsum, sh, &total);
+  }
+  if (big) {
+    team_sync<TW>();
+    return false;
+  }
+  if (per >= 2) {
+    for (uint32_t j = 0; j < per; j += 2) {
+      const uint32_t b = b0 + j;
+      if (b < nb) {
+        const uint32_t v0 = c16_get(cnt, b), v1 = c16_get(cnt, b + 1);
+        cnt[b >> 1] = base | ((base + v0) << 16);
+        base += v0 + v1;
+      }
+    }
+  }
+  team_sync<TW>();
+  if (per < 2) {  // thread tid owns bucket tid; even and odd neighbours share a word
+    const uint32_t b = b0;
+    const uint32_t mine = (b < nb) ? base : 0u;
+    const uint32_t other = __shfl_xor(mine, 1);
+    team_sync<TW>();
+    if (b < nb && (b & 1u) == 0u) cnt[b >> 1] = mine | (other << 16);
+    team_sync<TW>();
+  }
+  return true;
+}
+
+// The fallback sort of a group whose range needs more than 51 bits (bits, of
+// smallest key mn), which the packed words (x - min) << 12 | position cannot
+// hold: as many buckets as it takes for the offset inside a bucket to fit 52
+// bits, words (offset << 12) | position, and each slot's bucket found among
+// the bucket ends (the words do not hold it).  The payloads are in pb by
+// position already.  The keys are read from src twice (counts, words), both
+// before the barrier after which anything is stored, so a group may be
+// sorted in place.  Returns false, having stored nothing in dst, if the ncnt
+// 16-bit counters cannot hold the buckets or some bucket holds more than
+// kBucketMax keys.
+template <int PW, int TW>
+__device__ bool wide_bucket_sort(uint64_t* kb, const typename PayT<PW>::T* pb, uint32_t* cnt,
+                                 uint32_t ncnt, uint32_t* sh, const uint64_t* src, uint64_t* dst,
+                                 void* pdst, uint64_t start, uint32_t n, uint32_t tid,
+                                 uint64_t mn, int bits) {
+  constexpr uint32_t TT = TW * kWave;
+  uint32_t nb = 64;
+  int d = 6;
+  while (nb < n || (bits - d > 52 && nb < ncnt)) {
+    nb <<= 1;
+    ++d;
+  }
+  if (bits - d > 52 || nb > ncnt) return false;
+  const int shb = bits - d;
+  const uint64_t in_bucket = (1ull << shb) - 1ull;
+  for (uint32_t i = tid; i < nb / 2; i += TT) cnt[i] = 0;
+  team_sync<TW>();
+  for (uint32_t i = tid; i < n; i += TT) {
+    const uint32_t b = (uint32_t)((src[start + i] - mn) >> shb);
+    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) * 16u));
+  }
+  team_sync<TW>();
+  if (!bucket_starts<TW>(cnt, nb, sh, tid)) return false;
+  for (uint32_t i = tid; i < n; i += TT) {
+    const uint64_t dlt = src[start + i] - mn;
+    const uint32_t b = (uint32_t)(dlt >> shb);
+    const uint32_t sft = (b & 1u) * 16u;
+    const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sft);
+    const uint32_t pos = min((old >> sft) & 0xFFFFu, n - 1);
+    kb[pos] = ((dlt & in_bucket) << 12) | i;
+  }
+  team_sync<TW>();
+  // bucket b now spans [end(b-1), end(b)); slots in order, so the keys and
+  // payloads are stored nearly sequentially
+  for (uint32_t i = tid; i < n; i += TT) {
+    const uint64_t v = kb[i];
+    uint32_t lo = 0, hi = nb - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (c16_get(cnt, mid) > i) hi = mid;
+      else lo = mid + 1;
+    }
+    const uint32_t e = c16_get(cnt, lo);
+    const uint32_t s0 = lo ? c16_get(cnt, lo - 1) : 0u;
+    uint32_t rank = 0;
+    for (uint32_t j = s0; j < e; ++j) rank += kb[j] < v ? 1u : 0u;
+    const uint32_t p = min(s0 + rank, n - 1);
+    dst[start + p] = mn + ((uint64_t)lo << shb) + (v >> 12);
+    if constexpr (PW != 0) pay_store<PW>(pdst, start + p, pb[v & 4095u]);
+  }
+  team_sync<TW>();
+  return true;
+}
+
+
+// One wave's sort of a group held in its registers (key i = r * 64 + lane),
+// for any key range: as many buckets as the group has keys and as it takes
+// for the offset inside a bucket to fit 52 bits (at most ncnt 16-bit
+// counters), words (offset << 12) | position placed in bucket order with
+// each slot's bucket beside them in bkt, and each slot's key rebuilt from
+// its bucket and offset.  Nothing is read from memory but LDS (the payloads
+// go to pb by position), so the group may be sorted in place.  Returns
+// false, having stored nothing, if the counters cannot hold the buckets or
+// some bucket holds more than kBucketMax keys.
+template <int PW, int R>
+__device__ bool wide_wave_sort(uint64_t* kb, uint16_t* bkt, typename PayT<PW>::T* pb,
+                               uint32_t* cnt, uint32_t ncnt, uint64_t* dst, void* pdst,
+                               uint64_t start, uint32_t n, uint32_t ln, const uint64_t (&key)[R],
+                               const typename PayT<PW>::T (&pay)[R]) {
+  uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r * kWave + ln < n) {
+      mn = key[r] < mn ? key[r] : mn;
+      mx = key[r] > mx ? key[r] : mx;
+    }
+  }
+  wave_minmax_u64(mn, mx);
+  const uint64_t range = mx - mn;
+  const int bits = range ? 64 - __clzll((long long)range) : 0;
+  uint32_t nb = 64;
+  int d = 6;
+  while (nb < n || (bits - d > 52 && nb < ncnt)) {
+    nb <<= 1;
+    ++d;
+  }
+  if (bits - d > 52 || nb > ncnt) return false;
+  const int shb = bits > d ? bits - d : 0;
+  const uint64_t in_bucket = (1ull << shb) - 1ull;
+  for (uint32_t i = ln; i < nb / 2; i += kWave) cnt[i] = 0;
+  team_sync<1>();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r * kWave + ln < n) {
+      const uint32_t b = (uint32_t)((key[r] - mn) >> shb);
+      atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) * 16u));
+    }
+  }
+  team_sync<1>();
+  if (!bucket_starts<1>(cnt, nb, nullptr, ln)) return false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = r * kWave + ln;
+    if (i < n) {
+      const uint64_t dlt = key[r] - mn;
+      const uint32_t b = (uint32_t)(dlt >> shb);
+      const uint32_t sft = (b & 1u) * 16u;
+      const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sft);
+      const uint32_t pos = min((old >> sft) & 0xFFFFu, n - 1);
+      kb[pos] = ((dlt & in_bucket) << 12) | i;
+      bkt[pos] = (uint16_t)b;
+      if constexpr (PW != 0) pb[i] = pay[r];
+    }
+  }
+  team_sync<1>();
+  // bucket b spans [end(b-1), end(b)); slots in order, so the keys and
+  // payloads are stored nearly sequentially
+  for (uint32_t i = ln; i < n; i += kWave) {
+    const uint64_t v = kb[i];
+    const uint32_t b = bkt[i];
+    const uint32_t e = c16_get(cnt, b);
+    const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
+    uint32_t rank = 0;
+    for (uint32_t j = s0; j < e; ++j) rank += kb[j] < v ? 1u : 0u;
+    const uint32_t p = min(s0 + rank, n - 1);
+    dst[start + p] = mn + ((uint64_t)b << shb) + (v >> 12);
+    if constexpr (PW != 0) pay_store<PW>(pdst, start + p, pb[v & 4095u]);
+  }
+  team_sync<1>();
+  return true;
+}
+
 // Sorts keys[start, start+n) of `src` into dst (and the payload alongside).
 // TW waves cooperate; tid = thread index inside the team; kb/pb = the team's
 // LDS key and payload areas (TW*1024 words + padding), cnt/tot = [TW][256]
-// and [256] counters, red = 2*TW words.
+// and [256] counters, red = 2*TW words; from cnt on, ncnt 16-bit counters
+// for the bucket sort of wide ranges.
 template <int PW, int TW>
 __device__ void team_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t (*cnt)[256],
                           uint32_t* tot, uint64_t* rmin, uint64_t* rmax, uint32_t* sh,
                           const uint64_t* __restrict__ src, const void* psrc,
                           uint64_t* __restrict__ dst, void* pdst, uint64_t start, uint32_t n,
-                          uint32_t tid) {
+                          uint32_t tid, uint32_t ncnt) {
   using P = typename PayT<PW>::T;
   constexpr uint32_t TT = TW * kWave;  // team threads
   const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
@@ -2014,8 +2342,12 @@ __device__ void team_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t (*cnt
     return;
   }
 
-  // wide range: stable LSD radix.  Wave-blocked layout: position
+  // wide range: buckets on the top bits where they take the group, else a
+  // stable LSD radix.  Wave-blocked layout: position
   // tw*1024 + r*64 + ln, so ranks follow positions wave by wave, round by round.
+  if (wide_bucket_sort<PW, TW>(kb, pb, &cnt[0][0], ncnt, sh, src, dst, pdst, start, n, tid, mn,
+                               bits))
+    return;
   P pay[kLocPer];
 #pragma unroll
   for (int r = 0; r < kLocPer; ++r) {
@@ -2089,43 +2421,6 @@ __device__ void team_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t (*cnt
   team_sync<TW>();
 }
 
-template <int PW>
-__global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
-  using Sm = LocSmem<PW>;
-  __shared__ Sm sm;
-  Ctl* c = ws.ctl;
-  // the host paces the levels by the next level's segment count, stored
-  // straight into its pinned memory (no copy in the stream)
-  if (ws.h_nseg && blockIdx.x == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&ws.h_nseg[L + 1], call_failed(c) ? 0u : c->nseg[(L + 1) & 1],
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  if (call_failed(c)) return;
-  const int S = L & 1;
-  const uint32_t nh = min(c->nhard[S], ws.leaf_cap);
-  uint64_t* __restrict__ dst = ws.keys[0];
-  void* pdst = ws.pay[0];
-  const uint32_t wv = wave(), ln = lane();
-  const int t = threadIdx.x;
-  // groups of > kWaveCap keys: the whole workgroup
-  for (uint32_t g = blockIdx.x; g < nh; g += gridDim.x) {
-    const Leaf lf = ws.hard[S][g];
-    if (lf.count <= (uint32_t)kWaveCap) continue;
-    team_sort<PW, kWaves>(sm.k, sm.pay, sm.cnt, sm.tot[0], sm.rmin, sm.rmax, sm.sh,
-                          ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count,
-                          (uint32_t)t);
-  }
-  __syncthreads();
-  // groups of <= kWaveCap keys: one wave each
-  constexpr uint32_t kWaveWords = kWaveCap + kWaveCap / 16;
-  uint64_t* kb = sm.k + wv * kWaveWords;
-  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
-  for (uint32_t g = blockIdx.x * kWaves + wv; g < nh; g += gridDim.x * kWaves) {
-    const Leaf lf = ws.hard[S][g];
-    if (lf.count > (uint32_t)kWaveCap) continue;
-    team_sort<PW, 1>(kb, pb, &sm.cnt[wv], sm.tot[wv], nullptr, nullptr, nullptr,
-                     ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count, ln);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // fast local sort: one counting pass on the top bits of x - min (about one
@@ -2134,12 +2429,8 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
 // the unique words ((x - min) << 12) | position, so the result is the stable
 // sort.  Returns false, before writing anything, if the group's range needs
 // more than 51 bits or some bucket holds more than kBucketMax keys; such
-// groups go to the fallback sort.
+// groups go to the fallback kernel (whose bucket sort takes the wide ones).
 // ---------------------------------------------------------------------------
-constexpr int kBucketMax = 128;
-
-constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2); }
-
 template <int PW>
 struct FastSmem {
   // block jobs use all of it; wave jobs a quarter each
@@ -2152,10 +2443,6 @@ struct FastSmem {
   uint64_t rmin[kWaves], rmax[kWaves];
   uint32_t sh[kWaves + 2];
 };
-
-__device__ __forceinline__ uint32_t c16_get(const uint32_t* c, uint32_t b) {
-  return (c[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
-}
 
 // a team's group into registers: key i = r * TT + tid of the group
 template <int PW, int TT, int R>
@@ -2235,56 +2522,7 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
     }
   }
   team_sync<TW>();
-  // exclusive scan of the counters; each thread owns nb/TT consecutive ones
-  const uint32_t per = (nb + TT - 1) / TT;  // even, >= 1 ... counters per thread
-  const uint32_t b0 = tid * per;
-  uint32_t tsum = 0, tmax = 0;
-  for (uint32_t j = 0; j < per; ++j) {
-    const uint32_t b = b0 + j;
-    if (b < nb) {
-      const uint32_t v = c16_get(cnt, b);
-      tsum += v;
-      tmax = v > tmax ? v : tmax;
-    }
-  }
-  uint32_t base;
-  // some bucket above kBucketMax keys (a ballot per wave)
-  uint32_t big = __ballot(tmax > (uint32_t)kBucketMax) != 0ull ? 1u : 0u;
-  if constexpr (TW == 1) {
-    base = wave_incl_sum(tsum) - tsum;
-  } else {
-    if (ln == 0) sh[tw] = big;
-    team_sync<TW>();
-    for (int q = 0; q < TW; ++q) big |= sh[q];
-    team_sync<TW>();
-    uint32_t total;
-    base = block_excl_sum<TW * kWave>(tsum, sh, &total);
-  }
-  if (big) {
-    team_sync<TW>();
-    return false;
-  }
-  // counters become exclusive starts (two 16-bit halves per word)
-  if (per >= 2) {
-    for (uint32_t j = 0; j < per; j += 2) {
-      const uint32_t b = b0 + j;
-      if (b < nb) {
-        const uint32_t v0 = c16_get(cnt, b), v1 = c16_get(cnt, b + 1);
-        cnt[b >> 1] = base | ((base + v0) << 16);
-        base += v0 + v1;
-      }
-    }
-  }
-  team_sync<TW>();
-  if (per < 2) {  // (nb < 2*TT) two threads share a word: serialize through a scan of pairs
-    // per == 1: thread tid owns bucket tid; build words from even/odd neighbours
-    const uint32_t b = b0;
-    uint32_t mine = (b < nb) ? base : 0u;
-    const uint32_t other = __shfl_xor(mine, 1);
-    team_sync<TW>();
-    if (b < nb && (b & 1u) == 0u) cnt[b >> 1] = mine | (other << 16);
-    team_sync<TW>();
-  }
+  if (!bucket_starts<TW>(cnt, nb, sh, tid)) return false;
   // place the words
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -2338,6 +2576,44 @@ __device__ void push_hard(Ws& ws, int S, const Leaf& lf) {
   const uint32_t h = atomicAdd(&ws.ctl->nhard[S], 1u);
   if (h < ws.leaf_cap) ws.hard[S][h] = lf;
   else atomicOr(&ws.ctl->error, ERR_LEAFCAP);
+}
+
+template <int PW>
+__global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
+  using Sm = LocSmem<PW>;
+  __shared__ Sm sm;
+  Ctl* c = ws.ctl;
+  // the host paces the levels by the next level's segment count, stored
+  // straight into its pinned memory (no copy in the stream)
+  if (ws.h_nseg && blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&ws.h_nseg[L + 1], call_failed(c) ? 0u : c->nseg[(L + 1) & 1],
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (call_failed(c)) return;
+  const int S = L & 1;
+  const uint32_t nh = min(c->nhard[S], ws.leaf_cap);
+  uint64_t* __restrict__ dst = ws.keys[0];
+  void* pdst = ws.pay[0];
+  const uint32_t wv = wave(), ln = lane();
+  const int t = threadIdx.x;
+  // groups of > kWaveCap keys: the whole workgroup
+  for (uint32_t g = blockIdx.x; g < nh; g += gridDim.x) {
+    const Leaf lf = ws.hard[S][g];
+    if (lf.count <= (uint32_t)kWaveCap) continue;
+    team_sort<PW, kWaves>(sm.k, sm.pay, sm.cnt, sm.cnt[kWaves], sm.rmin, sm.rmax, sm.sh,
+                          ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count,
+                          (uint32_t)t, 2 * kWaves * 256 * 2);
+  }
+  __syncthreads();
+  // groups of <= kWaveCap keys: one wave each
+  constexpr uint32_t kWaveWords = kWaveCap + kWaveCap / 16;
+  uint64_t* kb = sm.k + wv * kWaveWords;
+  typename PayT<PW>::T* pb = sm.pay + (PW ? wv * kWaveCap : 0);
+  for (uint32_t g = blockIdx.x * kWaves + wv; g < nh; g += gridDim.x * kWaves) {
+    const Leaf lf = ws.hard[S][g];
+    if (lf.count > (uint32_t)kWaveCap) continue;
+    team_sort<PW, 1>(kb, pb, &sm.cnt[wv], sm.cnt[kWaves + wv], nullptr, nullptr, nullptr,
+                     ws.keys[lf.src], ws.pay[lf.src], dst, pdst, lf.start, lf.count, ln, 256 * 2);
+  }
 }
 
 template <int PW>
@@ -2488,6 +2764,51 @@ __global__ void __launch_bounds__(kWave) k_local_mid(Ws ws, int L) {
                                                       nullptr, ws.keys[lf.src], ws.pay[lf.src],
                                                       dst, pdst, lf.start, n, ln);
     if (!ok && ln == 0) push_hard(ws, S, lf);
+  }
+  // Wave jobs whose keys may span 2^51 or more (so the classification says):
+  // the fast sort if the range turns out to fit it, else the sort for any
+  // range, the next group's keys loaded meanwhile; a group neither takes
+  // goes to the fallback kernel.  A group has at most kWaveCap keys: the
+  // second half of the key area holds the slots' buckets.
+  {
+    using P = typename PayT<PW>::T;
+    constexpr int RX = kWaveCap / kWave;
+    static_assert(2 * kWaveCap <= kMidCap, "bucket ids beside the words");
+    uint16_t* bkt = reinterpret_cast<uint16_t*>(sm.k + kWaveCap);
+    const uint32_t nx = min(c->nleafx[S], ws.leaf_cap);
+    uint32_t gx = blockIdx.x;
+    Leaf xf{};
+    uint64_t xkey[RX];
+    P xpay[RX];
+    if (gx < nx) {
+      xf = ws.leavesx[S][gx];
+      group_load<PW, kWave, RX>(ws.keys[xf.src], ws.pay[xf.src], xf.start, xf.count, ln, xkey, xpay);
+    }
+    for (; gx < nx; gx += gridDim.x) {
+      const uint32_t gn = gx + gridDim.x;
+      Leaf nf{};
+      uint64_t nkey[RX];
+      P npay[RX];
+      if (gn < nx) {
+        nf = ws.leavesx[S][gn];
+        group_load<PW, kWave, RX>(ws.keys[nf.src], ws.pay[nf.src], nf.start, nf.count, ln, nkey,
+                                  npay);
+      }
+      moved += xf.count;
+      const bool ok =
+          fast_sort_regs<PW, 1, RX>(sm.k, sm.pay, sm.cnt, nullptr, nullptr, nullptr,
+                                    ws.keys[xf.src], ws.pay[xf.src], dst, pdst, xf.start, xf.count,
+                                    ln, xkey, xpay) ||
+          wide_wave_sort<PW, RX>(sm.k, bkt, sm.pay, sm.cnt, kMidCap, dst, pdst, xf.start, xf.count,
+                                 ln, xkey, xpay);
+      if (!ok && ln == 0) push_hard(ws, S, xf);
+      xf = nf;
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        xkey[r] = nkey[r];
+        xpay[r] = npay[r];
+      }
+    }
   }
   if (ln == 0 && moved) atomicAdd((unsigned long long*)&c->local_keys, (unsigned long long)moved);
 }

@@ -16,6 +16,7 @@ from .gen import (  # noqa: F401
     zipf,
     gmm,
     segments,
+    wide_range_arrays,
     make,
     WORKLOADS,
     small_range,

@@ -142,6 +142,34 @@ def segments(nseg: int, seed: int, median: float = 2e4, sigma_ln: float = 1.0,
     return keys, off, idx
 
 
+def wide_range_arrays(seed: int):
+    """Arrays whose keys span 2^52 .. 2^64 (ranges wider than a 52-bit offset
+    next to a 12-bit position), each short enough to be one leaf at cutoff
+    4096: uniform over [b, b + 2^w) for w in {53, 56, 60, 64} at lengths
+    around one wave's and one workgroup's share, a few distinct values spread
+    over 2^58 (repeats of ~40 and of ~400 per value), and three keys spanning
+    2^63.  Returns (keys, offsets[m+1]) of the m arrays laid end to end."""
+    rng = _rng(seed)
+    spec = [(3000, 56, 0), (2000, 64, 0), (400, 60, 0), (400, 64, 0), (700, 53, 0),
+            (600, 55, 0), (4096, 64, 0), (513, 58, 0), (2000, 58, 50), (2000, 58, 5),
+            (450, 58, 12), (3, 63, 0)]
+    arrays = []
+    for n, w, distinct in spec:
+        span = 1 << w
+        base = int(rng.integers(0, 2**64 - span + 1, dtype=np.uint64)) if w < 64 else 0
+        if distinct:
+            vals = rng.integers(0, span, size=distinct, dtype=np.uint64)
+            x = vals[rng.integers(0, distinct, size=n)]
+        elif w == 64:
+            x = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64, endpoint=True)
+        else:
+            x = rng.integers(0, span, size=n, dtype=np.uint64)
+        arrays.append((np.uint64(base) + x).astype(np.uint64))
+    off = np.zeros(len(arrays) + 1, dtype=np.int64)
+    np.cumsum([a.size for a in arrays], out=off[1:])
+    return np.concatenate(arrays), off
+
+
 def small_range(n: int, seed: int, span: int = 200) -> np.ndarray:
     """Restricted range: keys uniform over [b, b + span) for a random base b
     (the high-duplicate family of the paper draws from a restricted range)."""

@@ -83,6 +83,11 @@ def test_entry_points_reject_bad_arguments_without_touching_the_gpu():
         == zs.ZSORT_EINVAL
     assert L.zsort_stable_segmented(ctypes.c_void_p(16), None, 0, 10, None, 3, None, None) \
         == zs.ZSORT_EINVAL
+    # 128-bit keys: null or misaligned (not 16-byte) keys, n above the limit
+    assert L.zsort_stable_u128(None, None, 10, None, None, None) == zs.ZSORT_EINVAL
+    assert L.zsort_stable_u128(ctypes.c_void_p(24), None, 10, None, None, None) == zs.ZSORT_EINVAL
+    assert L.zsort_stable_u128(ctypes.c_void_p(32), None, 2**31, None, None, None) \
+        == zs.ZSORT_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -424,3 +424,54 @@ def test_counting_pass_trace_parity(cfg):
         zs.zsort_stable_ex(tk, tp, dict(cfg, count_range=0))
         torch.cuda.synchronize()
         assert zs.zsort_get_last_stats()["levels"] >= st["levels"]
+
+
+@pytest.mark.parametrize("pw", [0, 4, 8])
+def test_wide_range_leaves_vs_oracle(pw):
+    # Leaves whose keys span 2^53 .. 2^64, each array one leaf sorted in place
+    # (cutoff 4096): the fallback kernel's bucket sort (offset in a bucket up
+    # to 52 bits), and its radix sort where the counters cannot hold the
+    # buckets (a wave's share spanning 2^64, three keys spanning 2^63) or a
+    # bucket overflows (five values repeated ~400 times)
+    keys, off = synth.wide_range_arrays(synth.seed_for(40))
+    seg = np.repeat(np.arange(off.size - 1), np.diff(off))
+    if pw == 4:
+        pay = (np.arange(keys.size, dtype=np.int64) - off[seg]).astype(np.uint32)
+    elif pw == 8:
+        pay = np.random.default_rng(synth.seed_for(40, 1)).integers(
+            0, 2**64 - 1, size=keys.size, dtype=np.uint64, endpoint=True)
+    else:
+        pay = None
+    cfg = dict(k=256, cutoff=4096, max_zlevels=8, chunk=16384)
+    say(f"case wide-range leaves pw={pw} n={keys.size}")
+    tk, tp = to_dev(keys, pay)
+    zs.zsort_stable_segmented(tk, torch.from_numpy(off).to(DEV), tp, cfg)
+    torch.cuda.synchronize()
+    assert zs.zsort_get_last_stats()["device_error"] == 0
+    k, p = from_dev(tk, tp, None if pay is None else pay.dtype)
+    ok, op = oracle.sort_segmented(keys, off, pay, k=256, cutoff=4096, max_zlevels=8)
+    assert np.array_equal(k, ok)
+    if pw:
+        assert np.array_equal(p, op)
+
+
+@pytest.mark.parametrize("k,pw,name", [(256, 4, "uniform"), (2048, 8, "uniform"),
+                                       (2048, 0, "uniform"), (2048, 4, "dup_heavy")])
+def test_wide_range_leaves_after_a_pass_vs_oracle(k, pw, name):
+    # one level over uniform 64-bit keys: leaves of ~3900 (k 256) or ~490
+    # (k 2048) keys spanning ~2^56 or ~2^53, sorted from the other buffer; the
+    # k 2048 groups go straight to the wide wave jobs.  dup_heavy: 5000 values
+    # repeated ~200 times, groups of two or three of them, which overflow a
+    # bucket and go on to the fallback kernel
+    n = 1_000_000
+    x, pay = synth.make(name, n, payload_bytes=pw)
+    if name == "dup_heavy":
+        x = synth.dup_heavy(n, synth.seed_for(41), distinct=5000)
+    cfg = dict(k=k, cutoff=4096, max_zlevels=1, chunk=16384)
+    say(f"case wide-range leaves after a pass k={k} pw={pw} {name}")
+    kk, p, st = gpu_sort(x, pay, cfg)
+    assert st["device_error"] == 0
+    ok, op, _ = oracle.sort(x, pay, k=k, cutoff=4096, max_zlevels=1)
+    assert np.array_equal(kk, ok)
+    if pw:
+        assert np.array_equal(p, op)

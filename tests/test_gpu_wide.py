@@ -40,6 +40,9 @@ def test_u128_families_vs_oracle(name, cfg):
     assert rep["device_error"] == 0, rep
     ok, op = oracle.sort128(keys, idx)
     assert np.array_equal(k, ok) and np.array_equal(p, op)
+    # without a payload the high words carry the low words themselves
+    k2, _, rep2 = run128(keys, None, cfg)
+    assert rep2["device_error"] == 0 and np.array_equal(k2, ok)
     if name == "narrow":
         assert rep["short_runs"] > 0
     if name == "prefix":   # 1000 runs of ~300 keys: listed, then sorted as leaves
