@@ -584,6 +584,32 @@ def summarize_profiles(d, workload, cfg):
     print(f"wrote kernels_{tag}.md, traffic_{tag}.md, traffic_{workload}.json (dominant {dom})")
 
 
+def summarize_trace(d, label):
+    """Kernel time only, from one rocprofv3 kernel-trace run of this script
+    (`d` holds kt/ and commands.txt with a "kt: ..." line): the summary of an
+    extra line (learned map, batched graph, 128-bit keys), whose kernels are
+    not all distribution stages."""
+    cmds = {}
+    with open(os.path.join(d, "commands.txt")) as fh:
+        for ln in fh:
+            if ":" in ln:
+                a, b = ln.split(":", 1)
+                cmds[a.strip()] = b.strip()
+    rows = _csv(os.path.join(d, "kt"), "_kernel_stats.csv")
+    lines = [f"# Kernel time, {label}", "", "Command (from the repository root):", "",
+             "    " + cmds.get("kt", "?"), "",
+             "| kernel | stage | calls | total ms | avg us | % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        st = _stage_of(r["Name"]) or "-"
+        nm = r["Name"].replace("void ", "").replace("(zs::Ws, int)", "").replace("|", "/")
+        lines.append(f"| `{nm[:70]}` | {st} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {r['Percentage']} |")
+    out = os.path.join(ROOT, "profiles", f"kernels_{label}.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {os.path.relpath(out, ROOT)}")
+
+
 def measured_copy_gbs(dev, reps=5):
     """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
     (1 GiB read + 1 GiB written), median of `reps`, in GB/s of read + write."""
@@ -687,6 +713,8 @@ def main():
     ap.add_argument("--config", default=None,
                     help="fixed configuration for the primary workload instead of the "
                          "autotuner's, e.g. k=256,cutoff=2048,chunk=32768,tile=4096")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "LABEL"),
+                    help="write profiles/kernels_LABEL.md from one kernel-trace run in DIR")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 csv output and exit")
     ap.add_argument("--autotune", action="store_true",
@@ -695,6 +723,9 @@ def main():
                     help="workload of the main line: primary (lognormal + u64 index) or one of "
                          + ", ".join(EXTRAS) + " (profiling runs)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_profiles:
         if not args.config:
             raise SystemExit("--summarize-profiles needs the --config the profiled runs used")
