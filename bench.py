@@ -318,12 +318,9 @@ def run_u128(dev, n=10**8, steps=4):
         k, p = base_k.clone(), base_p.clone()
         rep = zs.zsort_stable_u128(k, p, cfg, report=True)    # warm-up + the levels
         assert rep["device_error"] == 0, rep
-        ks = k.view(-1, 2)
-        kk = (ks[:, 1] ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev))
-        same = kk[1:] == kk[:-1]
-        lo = ks[:, 0] ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev)
-        assert bool(((kk[1:] > kk[:-1]) | (same & (lo[1:] >= lo[:-1]))).all()), "not sorted"
-        del k, p, ks, kk, lo, same
+        from tests.invariants import check_stable_sorted128_device
+        check_stable_sorted128_device(base_k.view(-1, 2), k.view(-1, 2), p)
+        del k, p
         ins = [(base_k.clone(), base_p.clone()) for _ in range(steps)]
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)

@@ -71,6 +71,37 @@ def check_stable_sorted_device(k_in, k_out, idx_out):
     assert bool((idx[1:][eq] > idx[:-1][eq]).all()), "equal keys out of input order"
 
 
+def check_stable_sorted128_device(k_in, k_out, idx_out):
+    """128-bit keys as (n, 2) int64 tensors, low word first, ordered as
+    unsigned 128-bit numbers: sorted, a permutation whose index carries its
+    key (both words), stable."""
+    import torch
+    n = k_out.shape[0]
+    assert k_in.shape[0] == n, "size changed"
+    if n == 0:
+        return
+    hi = _unsigned_order(k_out[:, 1])
+    lo = _unsigned_order(k_out[:, 0])
+    same_hi = hi[1:] == hi[:-1]
+    assert bool(((hi[1:] > hi[:-1]) | (same_hi & (lo[1:] >= lo[:-1]))).all()), \
+        "keys not non-decreasing"
+    if idx_out is None:
+        return
+    idx = _as_index(idx_out)
+    assert int(idx.min()) >= 0 and int(idx.max()) < n, "index out of range"
+    seen = torch.zeros(n, dtype=torch.int8, device=k_out.device)
+    seen.index_fill_(0, idx, 1)
+    assert int(seen.sum(dtype=torch.int64)) == n, "index payload is not a permutation"
+    # each word gathered on its own: torch's row gather of an (n, 2) tensor
+    # (k_in[idx], index_select) returns wrong rows past the first n - 2^26 on
+    # this ROCm build once n exceeds 2^26, where one-dimensional gathers are right
+    for w in (0, 1):
+        assert bool((k_in[:, w].contiguous()[idx] == k_out[:, w]).all()), \
+            "key does not match its index"
+    eq = same_hi & (lo[1:] == lo[:-1])
+    assert bool((idx[1:][eq] > idx[:-1][eq]).all()), "equal keys out of input order"
+
+
 def check_segmented_stable_sorted_device(k_in, k_out, idx_out, offsets):
     """The three properties inside every segment [off[i], off[i+1]): the
     payload is each key's index within its own segment."""

@@ -16,7 +16,7 @@ import bench
 import oracle
 import synth
 from tests.invariants import (check_segmented_stable_sorted_device,
-                              check_stable_sorted_device)
+                              check_stable_sorted128_device, check_stable_sorted_device)
 
 torch = pytest.importorskip("torch")
 zs = pytest.importorskip("paper_2605_14419_amd")
@@ -119,3 +119,22 @@ def test_learned_1e8_invariants_on_device():
     st = zs.zsort_get_last_stats()
     assert st["device_error"] == 0, st
     check_stable_sorted_device(base_k, tk, tp)
+
+
+@pytest.mark.parametrize("name", ["uuid", "prefix", "zext"])
+def test_u128_1e8_invariants_on_device(name):
+    """128-bit keys at 10^8 with the u32 index, in the benchmark's
+    configuration: sorted, a permutation carrying its key, stable."""
+    n = 10**8
+    keys, idx = synth.make128(name, n)
+    say(f"case u128 1e8 {name}")
+    base_k = torch.from_numpy(keys.reshape(-1).view(np.int64)).to(DEV)
+    tp = torch.from_numpy(idx.view(np.int32)).to(DEV)
+    del keys, idx
+    tk = base_k.clone()
+    rep = zs.zsort_stable_u128(tk, tp, bench.TUNED["uniform_1e8"], report=True)
+    torch.cuda.synchronize()
+    assert rep["device_error"] == 0, rep
+    check_stable_sorted128_device(base_k.view(-1, 2), tk.view(-1, 2), tp)
+    del base_k, tk, tp
+    torch.cuda.empty_cache()

@@ -416,6 +416,41 @@ def test_device_checkers_reject_planted_mistakes_on_cpu_tensors():
         check_segmented_stable_sorted_device(kin, kout, iout, off)
 
 
+def test_device_checker128_rejects_planted_mistakes_on_cpu_tensors():
+    """The 128-bit form: (high, low) order with the high word deciding, the
+    index carrying both words, equal keys in input order."""
+    torch = pytest.importorskip("torch")
+    from tests.invariants import check_stable_sorted128_device
+    rng = np.random.default_rng(6)
+    hi = rng.integers(0, 3, size=300).astype(np.uint64) * np.uint64(2**63 // 2)
+    lo = rng.integers(0, 4, size=300).astype(np.uint64) * np.uint64(2**62)
+    order = np.lexsort((lo, hi))          # stable: equal keys keep input order
+    k2 = np.stack([lo, hi], axis=1)
+    kin = torch.from_numpy(k2.view(np.int64))
+    kout = torch.from_numpy(np.ascontiguousarray(k2[order]).view(np.int64))
+    iout = torch.from_numpy(order.astype(np.int32))
+    check_stable_sorted128_device(kin, kout, iout)
+    sk = k2[order]
+    eqpos = np.nonzero((sk[1:] == sk[:-1]).all(axis=1))[0][0]
+    bad_unstable = iout.clone()
+    bad_unstable[eqpos], bad_unstable[eqpos + 1] = iout[eqpos + 1], iout[eqpos]
+    # low words out of order inside a run of equal high words
+    run = np.nonzero((sk[1:, 1] == sk[:-1, 1]) & (sk[1:, 0] != sk[:-1, 0]))[0][0]
+    bad_lo = kout.clone()
+    bad_lo[run, 0], bad_lo[run + 1, 0] = kout[run + 1, 0], kout[run, 0]
+    bad_perm = iout.clone()
+    bad_perm[3] = bad_perm[4]
+    # a key whose low word differs from its index's key (still sorted: the
+    # last low word 0 becomes 1, below every other nonzero low word)
+    bad_word = kout.clone()
+    j = int(np.nonzero(sk[:, 0] == 0)[0][-1])
+    bad_word[j, 0] = 1
+    for k, i, what in [(kout, bad_unstable, "order"), (bad_lo, iout, "non-decreasing"),
+                       (kout, bad_perm, "permutation"), (bad_word, iout, "match")]:
+        with pytest.raises(AssertionError, match=what):
+            check_stable_sorted128_device(kin, k, i)
+
+
 # ---------------------------------------------------------------------------
 # 128-bit keys: the oracle's definition against brute force and a library sort
 # ---------------------------------------------------------------------------
