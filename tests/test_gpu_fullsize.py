@@ -1,6 +1,6 @@
 """GPU tests at the full sizes of the benchmark's workloads, in the
-configurations the benchmark runs (its recorded configuration per single-array
-workload; the library's autotuner for the batched and learned forms, as
+configurations the benchmark runs (its recorded configuration per workload
+and for the learned form; the library's autotuner for the batched form, as
 bench.py does).
 
 A stable sort has one correct output, which three properties pin without a
@@ -109,7 +109,7 @@ def test_learned_1e8_invariants_on_device():
     keys, idx = synth.make("gmm", n, payload_bytes=4)
     base_k, base_p = dev(keys, idx)
     del keys, idx
-    cfg = zs.zsort_autotune(base_k, base_p)
+    cfg = bench.TUNED["learned"]
     say(f"case learned 1e8 cfg={cfg}")
     tk, tp = base_k.clone(), base_p.clone()
     rep = zs.zsort_stable_learned(tk, tp, cfg, dict(flags=zs.ZSORT_LEARNED_ZSCORE_DIAG))
