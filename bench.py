@@ -611,6 +611,53 @@ def summarize_trace(d, label):
     print(f"wrote {os.path.relpath(out, ROOT)}")
 
 
+def summarize_counters(d, label):
+    """Hardware counters per distribution stage, from rocprofv3 --pmc runs of
+    this script (`d` holds p1/, p2/, ... and commands.txt with one "pN: ..."
+    line per pass): totals over every launch of the stage, and the ratios
+    that say where its time goes."""
+    cmds = []
+    with open(os.path.join(d, "commands.txt")) as fh:
+        cmds = [ln.strip() for ln in fh if ln.strip()]
+    agg = {}
+    for sub in sorted(os.listdir(d)):
+        if not os.path.isdir(os.path.join(d, sub)):
+            continue
+        for r in _csv(os.path.join(d, sub), "_counter_collection.csv"):
+            st = _stage_of(r["Kernel_Name"])
+            if st:
+                a = agg.setdefault(st, {})
+                a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    names = sorted({c for a in agg.values() for c in a})
+    lines = [f"# Hardware counters, {label}", "", "Commands (from the repository root):", ""]
+    lines += ["    " + c.split(":", 1)[1].strip() for c in cmds]
+    lines += ["", "Totals over every launch of each stage (all profiled sorts):", "",
+              "| stage | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for st in STAGES:
+        if st in agg:
+            lines.append(f"| {st} | " + " | ".join(f"{agg[st].get(c, 0):.3g}" for c in names) + " |")
+    def ratio(a, x, y):
+        return a[x] / a[y] if a.get(y) and x in a else float("nan")
+    lines += ["", "Ratios: waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES), VALU instructions "
+              "per wave cycle, LDS bank-conflict cycles per LDS-active cycle, share of 64-byte "
+              "write requests, share of 128-byte read requests.", "",
+              "| stage | waiting | VALU / wave cycle | LDS conflict / active | 64 B writes | 128 B reads |",
+              "|---|---|---|---|---|---|"]
+    for st in STAGES:
+        if st not in agg:
+            continue
+        a = agg[st]
+        lines.append(f"| {st} | {ratio(a, 'SQ_WAIT_ANY', 'SQ_WAVE_CYCLES'):.2f} | "
+                     f"{ratio(a, 'SQ_INSTS_VALU', 'SQ_WAVE_CYCLES'):.3f} | "
+                     f"{ratio(a, 'SQ_LDS_BANK_CONFLICT', 'SQ_ACTIVE_INST_LDS'):.2f} | "
+                     f"{ratio(a, 'TCC_EA0_WRREQ_64B_sum', 'TCC_EA0_WRREQ_sum'):.2f} | "
+                     f"{ratio(a, 'TCC_EA0_RDREQ_128B_sum', 'TCC_EA0_RDREQ_sum'):.2f} |")
+    out = os.path.join(ROOT, "profiles", f"counters_{label}.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {os.path.relpath(out, ROOT)}")
+
+
 def measured_copy_gbs(dev, reps=5):
     """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
     (1 GiB read + 1 GiB written), median of `reps`, in GB/s of read + write."""
@@ -714,6 +761,8 @@ def main():
     ap.add_argument("--config", default=None,
                     help="fixed configuration for the primary workload instead of the "
                          "autotuner's, e.g. k=256,cutoff=2048,chunk=32768,tile=4096")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("DIR", "LABEL"),
+                    help="write profiles/counters_LABEL.md from rocprofv3 --pmc runs in DIR")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "LABEL"),
                     help="write profiles/kernels_LABEL.md from one kernel-trace run in DIR")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -726,6 +775,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return
     if args.summarize_profiles:
         if not args.config:
