@@ -219,7 +219,10 @@ int zsort_stable_segmented(uint64_t* keys, void* payload, int payload_bytes, siz
  * of subproblems.  ZSORT_FLAG_SIGNED orders the keys as two's-complement
  * int128; ZSORT_FLAG_GRAPH returns ZSORT_EUNSUPPORTED; a misaligned keys
  * pointer ZSORT_EINVAL.  The stream keeps buffers of 16 bytes per key for the
- * stages (plus the workspace of the 64-bit sort with an 8-byte payload).  report (host, may be NULL) makes the call
+ * stages (plus the workspace of the 64-bit sort with an 8-byte payload).  The
+ * payload is rewritten in the caller's array between the stages: after an
+ * error in the second stage (a return code, or device_error in the report)
+ * the keys may be partly sorted and the payload no longer matches them.  report (host, may be NULL) makes the call
  * synchronous and receives the recursion depth of each stage and the runs.
  */
 typedef struct zsort_u128_report {
