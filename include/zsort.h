@@ -99,6 +99,17 @@ enum {
  *                over the keys).  zsort_stable_ex and zsort_stable_segmented
  *                only; the debug, traced and learned entry points return
  *                ZSORT_EUNSUPPORTED for it.
+ *                ZSORT_FLAG_FUSED_STATS: the statistics of a subproblem made
+ *                by a distribution pass (its exact min, max, sums of x and
+ *                x^2: Section III, the variance loop of Algorithm 1) are
+ *                accumulated while that pass scatters its keys, instead of in
+ *                a pass of their own over them at the next level.  Applies
+ *                with k <= 1024 (else ignored); output-neutral (the sums are
+ *                exact integers in either order).  Off by default: it saves
+ *                the 8 B/key re-read but its digit arithmetic and per-tile
+ *                accumulator updates cost more than that read (about 2x the
+ *                sort time on 10^8 lognormal keys, 10x on Zipf keys, whose
+ *                tiles are dominated by one cluster).
  *   count_range  0 (default: off) or 1..k: a subproblem whose keys span less
  *                than count_range (max - min < count_range) is finished by one
  *                stable counting pass on x - min (the counting-sort heuristic
@@ -108,6 +119,7 @@ enum {
  */
 #define ZSORT_FLAG_GRAPH 1
 #define ZSORT_FLAG_SIGNED 2
+#define ZSORT_FLAG_FUSED_STATS 4
 typedef struct zsort_config {
   int32_t k;
   int32_t cutoff;
@@ -282,7 +294,10 @@ int zsort_set_alloc_limit(size_t max_bytes);
  *                     with consistent counts), 0x100 malformed segment offsets
  *   keys_per_level    keys distributed at each level
  *   segs_per_level    subproblems distributed at each level
- *   mkeys_per_level   keys whose moments were taken at each level
+ *   mkeys_per_level   keys a moments pass read at each level (with
+ *                     ZSORT_FLAG_FUSED_STATS the statistics of a distribution
+ *                     pass's subproblems come from that pass's scatter, and
+ *                     their keys are not read again for them)
  *   local_keys        keys the local kernel sorted or copied into place
  *   model_bytes       algorithmic HBM bytes of the executed pass structure:
  *                     8 B per key of a moments pass, 8 B per key of a

@@ -33,6 +33,7 @@ EXPORTED = [
 ]
 ZSORT_FLAG_GRAPH = 1
 ZSORT_FLAG_SIGNED = 2
+ZSORT_FLAG_FUSED_STATS = 4
 ZSORT_MLP_PARAMS = 1153
 MLP_PARAMS_BYTES = 4872   # sizeof(zsort_mlp_params): 64 binary64, 1089 binary32, padding
 ZSORT_LEARNED_DIRECT = 1

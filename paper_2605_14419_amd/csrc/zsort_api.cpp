@@ -77,11 +77,12 @@ struct Shape {
   uint64_t n = 0;
   int pw = 0, k = 0, cutoff = 0, chunk = 0, tile = 0;
   int kfirst = 0;  // clusters of a learned first pass (0: none)
+  int fuse = 0;    // fused statistics: the child-of-cluster array is laid out
   int64_t nseg = 0;
   int64_t trace_cap = 0, trace_hist_cap = 0;
   bool operator==(const Shape& o) const {
     return n == o.n && pw == o.pw && k == o.k && cutoff == o.cutoff && chunk == o.chunk &&
-           tile == o.tile && kfirst == o.kfirst &&
+           tile == o.tile && kfirst == o.kfirst && fuse == o.fuse &&
            nseg == o.nseg && trace_cap == o.trace_cap && trace_hist_cap == o.trace_hist_cap;
   }
 };
@@ -92,6 +93,8 @@ struct Layout {
       off_hard[2],
       off_status, off_arrive[2], off_part,
       off_bstart, off_subpre, off_tiles[2], off_trace, off_thist, total;
+  size_t off_child, off_facc;   // fused statistics only (has_child)
+  bool has_child;
   size_t status_bytes;
   uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
 };
@@ -145,6 +148,9 @@ Layout plan(const Shape& s) {
   for (int i = 0; i < 2; ++i) L.off_arrive[i] = take(status_cap * 4);
   L.off_part = take(work_cap * 10 * 8);
   L.off_bstart = take(std::max<size_t>(seg_cap * (size_t)s.k, (size_t)s.kfirst) * 4);
+  L.has_child = s.fuse != 0;
+  L.off_child = L.has_child ? take(seg_cap * (size_t)s.k * 4) : 0;
+  L.off_facc = L.has_child ? take(seg_cap * 10 * 8) : 0;
   // 8192-key tiles: one row of k 16-bit prefix counts per 8192 keys
   const size_t krow = std::max<size_t>((size_t)s.k, s.kfirst <= 1024 ? (size_t)s.kfirst : 0);
   L.off_subpre = take(s.tile == 8192 ? ((n >> 13) + 2) * krow * 2 : 0);
@@ -266,6 +272,12 @@ int check_cfg(const zsort_config* c) {
   return ZSORT_OK;
 }
 
+// fused statistics: asked for, and with k <= 1024 (a cluster per thread or
+// more threads per cluster in the scatter's workgroup)
+bool fused_on(const zsort_config& c) {
+  return (c.flags & ZSORT_FLAG_FUSED_STATS) != 0 && c.k <= 1024;
+}
+
 int floor_log2(int k) {
   int lb = 0;
   while ((2 << lb) <= k) ++lb;
@@ -363,6 +375,8 @@ Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay
   for (int i = 0; i < 2; ++i) ws.arrive[i] = (uint32_t*)(base + L.off_arrive[i]);
   ws.part = (uint64_t*)(base + L.off_part);
   ws.bstart = (uint32_t*)(base + L.off_bstart);
+  ws.child_of = L.has_child ? (uint32_t*)(base + L.off_child) : nullptr;
+  ws.facc = L.has_child ? (uint64_t*)(base + L.off_facc) : nullptr;
   ws.subpre = (uint16_t*)(base + L.off_subpre);
   for (int i = 0; i < 2; ++i) ws.tiles[i] = (uint64_t*)(base + L.off_tiles[i]);
   ws.ctl = (zs::Ctl*)(base + L.off_ctl);
@@ -385,6 +399,7 @@ Ws ws_at(char* base, const Layout& L, const Shape& sh, uint64_t* keys, void* pay
   ws.p.tile = c.tile;
   ws.p.pw = pw;
   ws.p.count_range = c.count_range;
+  ws.p.fuse = (L.has_child && fused_on(c)) ? 1 : 0;
   return ws;
 }
 
@@ -465,6 +480,7 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   s.cutoff = c.cfg.cutoff;
   s.chunk = c.cfg.chunk;
   s.tile = c.cfg.tile;
+  s.fuse = fused_on(c.cfg) ? 1 : 0;
   s.nseg = c.off ? c.nseg : (c.runs ? c.runs_cap : 0);
   s.trace_cap = c.trace_cap;
   s.trace_hist_cap = c.hist_cap;
@@ -479,8 +495,8 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
                      !c.runs && !capturing(st);
   if (graph) {
     GraphKey gk{c.keys, c.pay, c.off, c.n, c.off ? c.nseg : 0, c.pw, c.cfg.k, c.cfg.cutoff,
-                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile, c.cfg.flags & ZSORT_FLAG_SIGNED,
-                c.cfg.count_range};
+                c.cfg.max_zlevels, c.cfg.chunk, c.cfg.tile,
+                c.cfg.flags & (ZSORT_FLAG_SIGNED | ZSORT_FLAG_FUSED_STATS), c.cfg.count_range};
     auto it = w->graphs.find(gk);
     hipGraphExec_t ex = nullptr;
     if (it != w->graphs.end()) {
@@ -758,6 +774,7 @@ Ws first_pass_ws(const Ws& ws, const LearnedWs* lw, int B, bool direct) {
   Ws w0 = ws;
   w0.p.k = B;
   w0.p.lb = floor_log2(B);
+  w0.p.fuse = 0;   // (the child-of-cluster array is laid out for the later levels' k)
   if (B > 1024) w0.p.tile = 2048;
   w0.lm.thr = lw->thr;
   w0.lm.par = lw->par;
@@ -821,6 +838,7 @@ int zsort_stable_noalloc(uint64_t* keys, void* payload, int payload_bytes, size_
   s.cutoff = c.cutoff;
   s.chunk = c.chunk;
   s.tile = c.tile;
+  s.fuse = fused_on(c) ? 1 : 0;
   const Layout L = plan(s);
   if (L.total > zs::kScratchBytes) return ZSORT_ETOOLARGE;
   int dev = 0;
@@ -931,7 +949,7 @@ int ctl_levels(hipStream_t st, int32_t* levels, int32_t* err) {
   if (e != hipSuccess) return hip_fail(e);
   int L = 0;
   for (int i = 0; i < zs::kMaxLevels; ++i)
-    if (ctl.lvl_mkeys[i]) L = i + 1;
+    if (ctl.lvl_mkeys[i] || ctl.lvl_fkeys[i]) L = i + 1;
   *levels = L;
   *err |= (int32_t)ctl.error;
   return ZSORT_OK;
@@ -1011,6 +1029,7 @@ size_t zsort_workspace_bytes(size_t n, int payload_bytes, int32_t num_segments,
   s.cutoff = c.cutoff;
   s.chunk = c.chunk;
   s.tile = c.tile;
+  s.fuse = fused_on(c) ? 1 : 0;
   s.nseg = num_segments > 0 ? num_segments : 0;
   return plan(s).total;
 }
@@ -1077,7 +1096,7 @@ int zsort_get_last_stats(void* stream, zsort_stats* out) {
     out->keys_per_level[L] = ctl.lvl_keys[L];
     out->mkeys_per_level[L] = ctl.lvl_mkeys[L];
     out->segs_per_level[L] = ctl.lvl_segs[L];
-    if (ctl.lvl_mkeys[L]) levels = L + 1;
+    if (ctl.lvl_mkeys[L] || ctl.lvl_fkeys[L]) levels = L + 1;
     bytes += 8.0 * (double)ctl.lvl_mkeys[L] + (8.0 + 2 * kp) * (double)ctl.lvl_keys[L];
   }
   bytes += 2 * kp * (double)ctl.local_keys + w->last_extra_bytes;
@@ -1457,6 +1476,7 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
   s.cutoff = c.cutoff;
   s.chunk = c.chunk;
   s.tile = c.tile;
+  s.fuse = fused_on(c) ? 1 : 0;
   s.kfirst = B;
   Workspace* w = nullptr;
   rc = acquire(st, s, &w);

@@ -72,7 +72,8 @@ enum : int32_t { KIND_PENDING = 0, KIND_IDENT = 1, KIND_ZMAP = 2, KIND_RMAP = 3,
 // kind of a counting pass in the recursion records of the public trace
 constexpr int32_t kTraceCount = 4;
 // segment flags
-enum : uint32_t { F_RMAP = 1u, F_ROOT = 2u };
+// F_FUSED: the statistics are accumulated by the parent's scatter
+enum : uint32_t { F_RMAP = 1u, F_ROOT = 2u, F_FUSED = 4u };
 // leaf-group flags
 enum : uint32_t { LF_COPY = 1u };
 
@@ -126,7 +127,8 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t ntrace_hist;
   // statistics of the call
   uint64_t lvl_keys[kMaxLevels]; // keys distributed at each level
-  uint64_t lvl_mkeys[kMaxLevels];// keys whose moments were taken at each level
+  uint64_t lvl_mkeys[kMaxLevels];// keys a moments pass read at each level
+  uint64_t lvl_fkeys[kMaxLevels];// keys whose statistics the parent's scatter accumulated
   uint32_t lvl_segs[kMaxLevels];
   uint32_t n_ident;
   uint32_t n_rmap;
@@ -209,6 +211,7 @@ struct Params {
   int32_t tile;          // keys per scatter tile (2048, 4096 or 8192)
   int32_t pw;            // payload bytes: 0, 4, 8
   int32_t count_range;   // > 0: subproblems with max - min < count_range take a counting pass
+  int32_t fuse;          // 1: children's statistics accumulated by their parent's scatter
 };
 
 // Everything a kernel needs, by value.
@@ -227,6 +230,9 @@ struct Ws {
                          // each unit's exclusive prefix over the segment's units
   uint64_t* part;        // per work item: 8 digit sums, min, max (moments pass)
   uint32_t* bstart;      // exclusive cluster starts relative to the segment, [seg][k]
+  uint32_t* child_of;    // fused statistics: each cluster's child segment (~0u: none), [seg][k]
+  uint64_t* facc;        // fused statistics: per child segment of the level being made, in
+                         // the order of the moments pass's partials (8 digit sums, min, max)
   uint32_t* arrive[2];   // per level slot: arrivals per scan unit, then per segment,
                          // indexed like the scan rows (zeroed when the segment is made)
   uint16_t* subpre;      // 8192-key tiles: each cluster's count in a work item before

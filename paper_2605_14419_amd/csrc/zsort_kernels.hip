@@ -525,6 +525,16 @@ __device__ void seg_clear_acc(Seg& s) {
   s.m = s.sigma = s.zmin = s.A = s.B = 0.0;
 }
 
+// a child (index idx of the level being made) whose statistics its parent's
+// scatter accumulates
+__device__ void seg_fuse_init(const Ws& ws, Seg& s, uint32_t idx) {
+  uint64_t* f = ws.facc + (uint64_t)idx * 10;
+  for (int j = 0; j < 8; ++j) f[j] = 0ull;
+  f[8] = ~0ull;
+  f[9] = 0ull;
+  s.flags |= F_FUSED;
+}
+
 __global__ void k_reset(Ws ws) {
   Ctl* c = ws.ctl;
   const int t = threadIdx.x;
@@ -532,6 +542,7 @@ __global__ void k_reset(Ws ws) {
     c->tick[t] = 0;
     c->lvl_keys[t] = 0;
     c->lvl_mkeys[t] = 0;
+    c->lvl_fkeys[t] = 0;
     c->lvl_segs[t] = 0;
   }
   if (t == 0) {
@@ -829,7 +840,7 @@ __device__ void trace_ident(Ws& ws, const Seg& s) {
 // control block once per wave (one atomic per segment on one address would
 // queue up behind each other)
 struct FinStat {
-  uint64_t mkeys = 0;
+  uint64_t mkeys = 0, fkeys = 0;
   uint32_t ident = 0, rmap = 0, count = 0;
 };
 
@@ -840,7 +851,8 @@ __device__ void finalize(Ws& ws, Seg& s, int L, const uint64_t (&acc)[10], FinSt
   const uint64_t M = acc[9];
   s.o = o;
   s.M = M;
-  fs.mkeys += cnt;
+  if (s.flags & F_FUSED) fs.fkeys += cnt;
+  else fs.mkeys += cnt;   // (keys the moments pass read)
 
   // raw sums: S1' = b0 + b1*2^32 ; S2' = a0 + a1*2^32 + a2*2^33 + a3*2^65 + a4*2^64 + a5*2^96
   W8 s1r = w8_zero();
@@ -948,6 +960,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
     const uint64_t item = ws.work[S][w];
     const uint32_t si = (uint32_t)(item >> 32), ci = (uint32_t)item;
     Seg& sg = ws.segs[S][si];
+    if (sg.flags & F_FUSED) continue;   // its parent's scatter took its statistics
     const uint64_t beg = sg.start + (uint64_t)ci * ch;
     const uint64_t end = min(beg + ch, sg.start + sg.count);
     uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, b0 = 0, b1 = 0;
@@ -1027,7 +1040,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   // segments of many chunks: a whole workgroup each
   for (uint32_t i = blockIdx.x; i < ns; i += gridDim.x) {
     Seg& sg = ws.segs[S][i];
-    if (sg.nchunks < kFinBig) continue;
+    if (sg.nchunks < kFinBig || (sg.flags & F_FUSED)) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
     sum_partials(ws.part + (uint64_t)sg.first_work * 10, threadIdx.x, sg.nchunks, kFinThreads, v);
     wave_reduce_moments(v);
@@ -1050,7 +1063,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   const uint32_t nwv = gridDim.x * NWV;
   for (uint32_t i = blockIdx.x * NWV + wv; i < ns; i += nwv) {
     Seg& sg = ws.segs[S][i];
-    if (sg.nchunks >= kFinBig || sg.nchunks <= kFinLane) continue;
+    if ((sg.flags & F_FUSED) || sg.nchunks >= kFinBig || sg.nchunks <= kFinLane) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
     sum_partials(ws.part + (uint64_t)sg.first_work * 10, ln, sg.nchunks, kWave, v);
     wave_reduce_moments(v);
@@ -1058,27 +1071,36 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(Ws ws, int L) {
   }
   // the many small segments of the deeper levels: one lane each, which sums
   // its few partials itself (the statistics are serial work of one lane in
-  // any case, so 64 of them run side by side)
+  // any case, so 64 of them run side by side); so do the segments whose
+  // statistics their parent's scatter accumulated
   const uint32_t nln = nwv * kWave;
   for (uint32_t i = (blockIdx.x * NWV + wv) * kWave + ln; i < ns; i += nln) {
     Seg& sg = ws.segs[S][i];
-    if (sg.nchunks > kFinLane) continue;
+    const bool fused = (sg.flags & F_FUSED) != 0;
+    if (!fused && sg.nchunks > kFinLane) continue;
     uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
-    sum_partials(ws.part + (uint64_t)sg.first_work * 10, 0u, sg.nchunks, 1u, v);
+    if (fused) {
+#pragma unroll
+      for (int j = 0; j < 10; ++j) v[j] = ws.facc[(uint64_t)i * 10 + j];
+    } else {
+      sum_partials(ws.part + (uint64_t)sg.first_work * 10, 0u, sg.nchunks, 1u, v);
+    }
     finalize(ws, sg, L, v, fs);
   }
   // statistics of the wave's segments
-  uint64_t mk = fs.mkeys;
+  uint64_t mk = fs.mkeys, fk = fs.fkeys;
   uint32_t id = fs.ident, rm = fs.rmap, ct = fs.count;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
     mk += __shfl_xor(mk, d);
+    fk += __shfl_xor(fk, d);
     id += __shfl_xor(id, d);
     rm += __shfl_xor(rm, d);
     ct += __shfl_xor(ct, d);
   }
   if (ln == 0) {
     if (mk) atomicAdd((unsigned long long*)&c->lvl_mkeys[L], (unsigned long long)mk);
+    if (fk) atomicAdd((unsigned long long*)&c->lvl_fkeys[L], (unsigned long long)fk);
     if (id) atomicAdd(&c->n_ident, id);
     if (ct) atomicAdd(&c->n_count, ct);
     if (rm) atomicAdd(&c->n_rmap, rm);
@@ -1153,7 +1175,7 @@ __device__ __forceinline__ int cluster_at(const HistSmem<KMAX>& sm, int k, uint3
   return lo;
 }
 
-template <int KMAX>
+template <int KMAX, bool FUSE>
 __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L) {
   Ctl* c = ws.ctl;
   const int k = ws.p.k;
@@ -1198,6 +1220,8 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
   }
   uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
   for (int b = t; b < k; b += kBlock) gb[b] = sm.bst[b];
+  // fused statistics: the children of a z-score or range-map segment
+  const bool fuse_children = FUSE && sg_kind != KIND_LMAP;
   // the four list allocations in one atomic instruction (four lanes): the
   // counters are shared by every workgroup of the level, so each round trip
   // is a long one
@@ -1249,6 +1273,7 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       clear_arrivals(ws.arrive[N] + sm.base_status + sm.t2[b], (n + ch - 1) / ch);
       cs.parent = (int32_t)si;
       seg_clear_acc(cs);
+      if (fuse_children) seg_fuse_init(ws, cs, idx);
       if (parent_l && ws.lm.sub) {
         // first stage of a two-stage learned map: the child is learned too,
         // with the sub - 1 thresholds after root threshold b
@@ -1262,6 +1287,10 @@ __device__ void classify(Ws& ws, HistSmem<KMAX>& sm, Seg& sg, uint32_t si, int L
       }
     }
     // work items of the children, in chunk order; t0 now maps child -> bucket
+    if (fuse_children)
+      for (int b = t; b < k; b += kBlock)
+        ws.child_of[(uint64_t)si * (uint64_t)k + b] =
+            (!counted && sm.h[b] > cutoff) ? sm.base_seg + sm.t0[b] : ~0u;
     __syncthreads();
     // child list: position by child index
     for (int b = t; b < k; b += kBlock)
@@ -1500,8 +1529,9 @@ __device__ __forceinline__ void hist_add(HistSmem<KMAX>& sm, uint32_t b, uint64_
 }
 
 // LM: 0 plain; the learned passes (every segment has KIND_LMAP): 1 with
-// thresholds, 2 with the MLP evaluated per key.  Separate instances, so that
-// the per-key MLP does not raise the register count of the other two.
+// thresholds, 2 with the MLP evaluated per key; 3 plain, and the children's
+// statistics are left to the scatter.  Separate instances, so that the
+// per-key MLP (or the fusion) does not raise the register count of the others.
 template <int KMAX, int LM>
 __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   __shared__ HistSmem<KMAX> sm;
@@ -1545,7 +1575,7 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
       }
     }
     __syncthreads();
-    if constexpr (LM != 0) {
+    if constexpr (LM == 1 || LM == 2) {
       // learned map: cluster = number of the segment's window thresholds
       // <= key (binary search in LDS), or the MLP evaluated per key; the ids
       // go to the scatter pass
@@ -1665,7 +1695,7 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
       }
     }
     __syncthreads();
-    if (seg_done) classify<KMAX>(ws, sm, sg, si, L);
+    if (seg_done) classify<KMAX, LM == 3>(ws, sm, sg, si, L);
     __syncthreads();
   }
   if (t == 0) {
@@ -1678,6 +1708,63 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
 // ---------------------------------------------------------------------------
 // scatter: stable, key + payload, through an LDS-staged tile
 // ---------------------------------------------------------------------------
+
+// Fused statistics of the children (Section III: the statistics of a
+// subproblem, the sums of Algorithm 1's mean and variance loops): once a
+// window of the tile is staged in cluster order, each cluster's keys in it
+// are summed like the moments pass sums a chunk (32-bit digit sums of x and
+// x^2, min, max) and added to its child's accumulators with device atomics
+// -- exact integer sums, so the order of the additions is free.  tpc threads
+// share a cluster (as many as the workgroup has per cluster, a power of two),
+// so a tile dominated by one cluster serialises on that cluster's threads;
+// cst holds each cluster's start in the tile (tn: the tile's key count),
+// stage the window [p0, p0 + pn) of the tile.
+template <int KMAX, int SB>
+__device__ __forceinline__ void fused_stats(const Ws& ws, const uint32_t* cof,
+                                            const uint16_t* cst, const uint64_t* stage, int k,
+                                            uint32_t tn, uint32_t p0, uint32_t pn, int t) {
+  uint32_t tpc = 1;
+  while (tpc * 2u * (uint32_t)k <= (uint32_t)SB) tpc <<= 1;
+  const uint32_t sub = (uint32_t)t % tpc, per = (uint32_t)SB / tpc;
+  for (uint32_t bb = 0; bb < (uint32_t)k; bb += per) {   // (the same trip count in every lane)
+    const uint32_t b = bb + (uint32_t)t / tpc;
+    uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, ~0ull, 0};
+    uint32_t cid = ~0u, r0 = 0, r1 = 0;
+    if (b < (uint32_t)k) {
+      cid = cof[b];
+      const uint32_t s0 = cst[b], s1 = b + 1 < (uint32_t)k ? cst[b + 1] : tn;
+      r0 = max(s0, p0);
+      r1 = min(s1, p0 + pn);
+      if (cid != ~0u)
+        for (uint32_t p = r0 + sub; p < r1; p += tpc) {
+          const uint64_t x = stage[p - p0];
+          const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+          const uint64_t ll = (uint64_t)xl * xl, lh = (uint64_t)xl * xh, hh = (uint64_t)xh * xh;
+          v[0] += (uint32_t)ll; v[1] += ll >> 32;
+          v[2] += (uint32_t)lh; v[3] += lh >> 32;
+          v[4] += (uint32_t)hh; v[5] += hh >> 32;
+          v[6] += xl; v[7] += xh;
+          v[8] = x < v[8] ? x : v[8];
+          v[9] = x > v[9] ? x : v[9];
+        }
+    }
+    for (uint32_t o = 1; o < tpc; o <<= 1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] += __shfl_xor(v[j], (int)o);
+      const uint64_t a = __shfl_xor(v[8], (int)o), z = __shfl_xor(v[9], (int)o);
+      v[8] = a < v[8] ? a : v[8];
+      v[9] = z > v[9] ? z : v[9];
+    }
+    if (sub == 0 && cid < ws.seg_cap && r1 > r0) {
+      uint64_t* f = ws.facc + (uint64_t)cid * 10;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (v[j]) atomicAdd((unsigned long long*)&f[j], (unsigned long long)v[j]);
+      atomicMin((unsigned long long*)&f[8], (unsigned long long)v[8]);
+      atomicMax((unsigned long long*)&f[9], (unsigned long long)v[9]);
+    }
+  }
+}
 template <int KMAX, int PW, int ROUNDS, int SB>
 struct ScatSmem {
   static constexpr int NWV = SB / kWave;           // waves of the workgroup
@@ -1698,7 +1785,9 @@ struct ScatSmem {
 // order through LDS windows of SW keys (the whole tile where it fits), so
 // each cluster's run per tile is T / k keys long.
 // (a workgroup of 1024 threads is one per CU: its register budget is 128)
-template <int KMAX, int KBITS, int PW, int ROUNDS, int SB>
+// FUSE: the instance that also accumulates the children's statistics (a
+// separate instance, so that the plain scatter keeps its registers)
+template <int KMAX, int KBITS, int PW, int ROUNDS, int SB, bool FUSE = false>
 __global__ void __launch_bounds__(SB, (SB >= 1024 ? 1 : (ROUNDS <= 8 ? 4 : 2))) k_scatter(Ws ws, int L) {
   using P = typename PayT<PW>::T;
   using Sm = ScatSmem<KMAX, PW, ROUNDS, SB>;
@@ -1768,6 +1857,9 @@ __global__ void __launch_bounds__(SB, (SB >= 1024 ? 1 : (ROUNDS <= 8 ? 4 : 2))) 
     const uint64_t end = min(beg + span, sg.start + sg.count);
     if (beg >= end) continue;
     const uint32_t* gb = ws.bstart + (uint64_t)si * (uint64_t)k;
+    // fused statistics: this segment's classification named each cluster's
+    // child (z-score and range-map segments only)
+    const uint32_t* cof = (FUSE && !lmap) ? ws.child_of + (uint64_t)si * (uint64_t)k : nullptr;
     // start of each cluster: the segment's exclusive start, the prefix of
     // the chunk's scan unit, the running count within the unit before the
     // chunk, and (8192-key tiles) the count before the tile within the chunk
@@ -1929,6 +2021,8 @@ __global__ void __launch_bounds__(SB, (SB >= 1024 ? 1 : (ROUNDS <= 8 ? 4 : 2))) 
             if constexpr (PW == 4) reinterpret_cast<uint32_t*>(pout)[d] = sm.spay4[p];
           }
         }
+        if constexpr (FUSE)
+          if (cof) fused_stats<KMAX, SB>(ws, cof, sm.cnt[0], sm.stage, k, tn, p0, pn, t);
         if constexpr (PW == 8) {   // 8-byte payloads: second round through the key stage
           using P2 = typename PayT<PW>::T;
           P2* spay = reinterpret_cast<P2*>(sm.stage);
@@ -2903,10 +2997,20 @@ static void launch_stage_t(const Ws& ws, int L, int stage, int grid, hipStream_t
         hipLaunchKernelGGL((k_hist<KMAX, 2>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       else if (ws.lm.ids)
         hipLaunchKernelGGL((k_hist<KMAX, 1>), dim3(grid), dim3(kBlock), 0, st, ws, L);
+      else if (KMAX <= 1024 && ws.p.fuse)
+        hipLaunchKernelGGL((k_hist<KMAX, (KMAX <= 1024 ? 3 : 0)>), dim3(grid), dim3(kBlock), 0, st,
+                           ws, L);
       else
         hipLaunchKernelGGL((k_hist<KMAX, 0>), dim3(grid), dim3(kBlock), 0, st, ws, L);
       break;
     case STAGE_SCATTER:
+      if constexpr (KMAX <= 1024) {
+        if (ws.p.fuse) {
+          hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS, SB, true>), dim3(grid), dim3(SB), 0,
+                             st, ws, L);
+          break;
+        }
+      }
       hipLaunchKernelGGL((k_scatter<KMAX, KBITS, PW, ROUNDS, SB>), dim3(grid), dim3(SB), 0, st, ws,
                          L);
       break;

@@ -143,3 +143,24 @@ def test_count_range_must_not_exceed_k():
     neg = zs.zsort_default_config(count_range=-1)
     assert L.zsort_stable_ex(ctypes.c_void_p(16), None, 0, 10, ctypes.byref(neg), None) \
         == zs.ZSORT_EINVAL
+
+
+def test_flag_constants_match_the_header():
+    src = open(os.path.join(ROOT, "include", "zsort.h")).read()
+    defs = dict(re.findall(r"^#define\s+(ZSORT_FLAG_\w+)\s+(\d+)", src, flags=re.M))
+    assert set(defs) == {"ZSORT_FLAG_GRAPH", "ZSORT_FLAG_SIGNED", "ZSORT_FLAG_FUSED_STATS"}
+    for name, v in defs.items():
+        assert getattr(zs, name) == int(v), name
+
+
+def test_fused_statistics_workspace():
+    """the fused layout adds the child-of-cluster array and the accumulators
+    (k <= 1024 only; larger k ignores the flag)"""
+    n = 10**7
+    for k in (256, 1024):
+        plain = zs.zsort_workspace_bytes(n, 4, 0, dict(k=k))
+        fused = zs.zsort_workspace_bytes(n, 4, 0, dict(k=k, flags=zs.ZSORT_FLAG_FUSED_STATS))
+        assert plain < fused <= plain + plain // 4, (k, plain, fused)
+    big = dict(k=4096, cutoff=2048, chunk=32768)
+    assert (zs.zsort_workspace_bytes(n, 4, 0, big) ==
+            zs.zsort_workspace_bytes(n, 4, 0, dict(big, flags=zs.ZSORT_FLAG_FUSED_STATS)))

@@ -26,7 +26,9 @@ def dev(keys, pay):
 
 @pytest.mark.parametrize("cfg,pw", [(None, 4),
                                     (dict(k=512, cutoff=1024, chunk=32768, tile=8192), 4),
-                                    (dict(k=256, cutoff=4096, chunk=32768, tile=8192), 8)])
+                                    (dict(k=256, cutoff=4096, chunk=32768, tile=8192), 8),
+                                    (dict(k=512, cutoff=1024, chunk=32768, tile=8192,
+                                          flags=4), 4)])
 def test_noalloc_matches_allocating_entry_point_twice(cfg, pw):
     runs = [("lognormal", 2**21 - 5 if pw == 8 else 3 * 10**6 + 7), ("dup_heavy", 100_003)]
     for name, n in runs:   # the second call is smaller than the first
