@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
@@ -196,8 +197,11 @@ struct Workspace {
   // per-kernel event timing (zsort_profile_begin / _end)
   bool prof = false;
   uint32_t prof_mask = 0;  // kernel kinds that are timed (bit = stage)
-  // pacing of level launches: per level, a host copy of the next level's
-  // segment count and an event recorded after the level's kernels
+  // pacing of level launches: the next level's segment count, stored by
+  // the kernels with the call's token (h_pace); the learned form hands its
+  // first levels' counts over by copies and events instead (h_nseg, lvl_ev)
+  uint64_t* h_pace = nullptr;  // pinned, kMaxLevels + 1 words
+  uint32_t pace_seq = 0;
   uint32_t* h_nseg = nullptr;  // pinned, kMaxLevels + 1 words
   hipEvent_t lvl_ev[zs::kMaxLevels] = {};
   bool lvl_ev_ok = false;
@@ -449,6 +453,14 @@ bool pacing_ready(Workspace* w) {
       return false;
     w->h_nseg = (uint32_t*)p;
   }
+  if (!w->h_pace) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, (zs::kMaxLevels + 1) * sizeof(uint64_t), hipHostMallocDefault) !=
+        hipSuccess)
+      return false;
+    std::memset(p, 0, (zs::kMaxLevels + 1) * sizeof(uint64_t));
+    w->h_pace = (uint64_t*)p;
+  }
   for (int i = 0; i < zs::kMaxLevels; ++i)
     if (!w->lvl_ev[i] && hipEventCreateWithFlags(&w->lvl_ev[i], hipEventDisableTiming) != hipSuccess)
       return false;
@@ -555,32 +567,96 @@ hipError_t enqueue(Workspace* w, const Ws& ws, const Call& c, hipStream_t st) {
   return e;
 }
 
-// levels L0, L0 + 1, ... (L0 > 0: level L0 - 1 ran already and recorded its
-// pacing event and segment count)
+// The word level L - 1's histogram pass stores for this call (token): level
+// L's segment count and whether level L - 1 has leaf jobs.  Returns
+// hipSuccess, or the stream's error.  If the stream drains without the store
+// (only a call that failed before that pass ends so), the count is read from
+// the device and the leaf jobs are taken to exist.  The stream is queried
+// only after 2 ms of waiting (a query can put a marker between the queued
+// kernels, a gap of ~5 us).
+hipError_t wait_pace(Workspace* w, const Ws& ws, int L, uint32_t token, hipStream_t st,
+                     uint32_t* count, bool* leaves) {
+  volatile uint64_t* slot = w->h_pace + L;
+  auto next = std::chrono::steady_clock::now() + std::chrono::milliseconds(2);
+  for (uint32_t spin = 1;; ++spin) {
+    uint64_t v = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
+    if (zs::pace_token_of(v) == token) {
+      *count = (uint32_t)v;
+      *leaves = zs::pace_leaves_of(v);
+      return hipSuccess;
+    }
+    if ((spin & 255u) == 0 && std::chrono::steady_clock::now() >= next) {
+      next += std::chrono::milliseconds(1);
+      const hipError_t q = hipStreamQuery(st);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return q;
+      v = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
+      if (zs::pace_token_of(v) == token) {
+        *count = (uint32_t)v;
+        *leaves = zs::pace_leaves_of(v);
+        return hipSuccess;
+      }
+      *leaves = true;
+      return hipMemcpy(count, &ws.ctl->nseg[L & 1], sizeof(uint32_t), hipMemcpyDeviceToHost);
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// levels L0, L0 + 1, ... (L0 > 0: level L0 - 1 ran already; with L0 >= 2
+// its segment count was copied to h_nseg[L0 - 1] before event lvl_ev[L0 - 2])
 hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0) {
   hipError_t e = hipSuccess;
   const int levels = c.level0_only ? 1 : levels_for(c.cfg);
-  // Pacing: level L >= 2 is launched only if level L-1 holds segments, which
-  // the host learns from a copy of the count taken after level L-2.  The host
-  // waits for level L-2 while level L-1 runs, so one level is always queued
-  // ahead of the device.  Under stream capture every level is launched (each
-  // kernel of an empty level exits at once).
+  // Pacing: once level L's histogram pass ends, its last workgroup stores
+  // level L + 1's segment count and whether level L has leaf jobs.  The host
+  // waits for that word while level L's scatter runs, then launches level
+  // L's local sorts if it has leaf jobs and level L + 1 if it has segments:
+  // no level after the last and no empty local stage is launched.  Under
+  // stream capture every level and stage is launched (each kernel without
+  // work exits at once).
   const bool paced = !c.level0_only && !capturing(st) && pacing_ready(w);
-  // (the last kernel of each level stores the next level's segment count in
-  // the pinned words; the event after it makes the store visible)
   Ws wsp = ws;
-  wsp.h_nseg = paced ? w->h_nseg : nullptr;
+  uint32_t token = 0;
+  if (paced) {
+    w->pace_seq = (w->pace_seq + 1u) & 0xFFFFFFu;
+    if (w->pace_seq == 0) w->pace_seq = 1;   // 0 would match the zeroed words
+    token = w->pace_seq;
+    wsp.h_pace = w->h_pace;
+    wsp.pace_token = token;
+  }
+  auto locals = [&](int L) {
+    hipError_t r = stage(w, wsp, L, zs::STAGE_LOCAL, grid_size(c.cfg.k, c.pw, c.cfg.tile,
+                                                               zs::STAGE_LOCAL), st);
+    if (r == hipSuccess)
+      r = stage(w, wsp, L, zs::STAGE_LOCAL_HARD,
+                grid_size(c.cfg.k, c.pw, c.cfg.tile, zs::STAGE_LOCAL_HARD), st);
+    return r;
+  };
+  int pending = -1;   // the level whose local sorts wait for its histogram pass's word
   for (int L = L0; L < levels && e == hipSuccess; ++L) {
-    if (paced && L >= 2) {
+    if (pending >= 0) {
+      uint32_t nseg = 0;
+      bool leaves = true;
+      e = wait_pace(w, ws, L, token, st, &nseg, &leaves);
+      if (e == hipSuccess && leaves) e = locals(pending);
+      pending = -1;
+      if (e != hipSuccess || nseg == 0) break;
+    } else if (paced && L >= 2) {   // the learned form's hand-over
       e = hipEventSynchronize(w->lvl_ev[L - 2]);
-      if (e != hipSuccess) break;
-      if (w->h_nseg[L - 1] == 0) break;
+      if (e != hipSuccess || w->h_nseg[L - 1] == 0) break;
     }
-    for (int sid = 0; sid < zs::NSTAGES && e == hipSuccess; ++sid) {
-      if (c.level0_only && (sid == zs::STAGE_LOCAL || sid == zs::STAGE_LOCAL_HARD)) continue;
+    for (int sid = zs::STAGE_MOMENTS; sid <= zs::STAGE_SCATTER && e == hipSuccess; ++sid)
       e = stage(w, wsp, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
-    }
-    if (paced && e == hipSuccess) e = hipEventRecord(w->lvl_ev[L], st);
+    if (e != hipSuccess || c.level0_only) continue;
+    if (paced) pending = L;
+    else e = locals(L);
+  }
+  if (e == hipSuccess && pending >= 0) {   // the last level launched
+    uint32_t nseg = 0;
+    bool leaves = true;
+    e = wait_pace(w, ws, pending + 1, token, st, &nseg, &leaves);
+    if (e == hipSuccess && leaves) e = locals(pending);
   }
   return e;
 }
@@ -1336,6 +1412,7 @@ int zsort_release(void) {
     for (hipEvent_t ev : w->lvl_ev)
       if (ev) (void)hipEventDestroy(ev);
     if (w->h_nseg) (void)hipHostFree(w->h_nseg);
+    if (w->h_pace) (void)hipHostFree(w->h_pace);
     delete w;
   };
   for (auto& kv : g_ws) free_ws(kv.second);

@@ -118,6 +118,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t nhard[2];             // groups the bucket pass left to the merge / radix sort
   uint32_t nstatus[2];
   uint32_t tick[kMaxLevels];     // work-item tickets of the hist pass
+  uint32_t hdone[kMaxLevels];    // workgroups of the hist pass that have finished
   uint32_t ntile[2];             // 8192-key tiles: entries of the scatter's tile list
   uint32_t epoch;                // changes every call; tags the scan rows
   uint32_t clear_epoch;          // epoch at which the scan rows were last cleared
@@ -214,6 +215,13 @@ struct Params {
   int32_t fuse;          // 1: children's statistics accumulated by their parent's scatter
 };
 
+// the word a histogram pass leaves for the host's pacing of the levels
+__host__ __device__ inline uint64_t pace_word(uint32_t token, uint32_t nseg, bool leaves) {
+  return ((uint64_t)(token & 0xFFFFFFu) << 40) | ((uint64_t)(leaves ? 1u : 0u) << 32) | nseg;
+}
+__host__ __device__ inline uint32_t pace_token_of(uint64_t w) { return (uint32_t)(w >> 40); }
+__host__ __device__ inline bool pace_leaves_of(uint64_t w) { return ((w >> 32) & 1u) != 0; }
+
 // Everything a kernel needs, by value.
 struct Ws {
   uint64_t* keys[2];     // [0] caller's buffer, [1] alternate buffer
@@ -242,8 +250,11 @@ struct Ws {
   TraceRec* trace;       // may be null
   uint32_t* trace_hist;
   uint32_t trace_cap, trace_hist_cap;
-  uint32_t* h_nseg;      // pinned host words, or null: the last kernel of level L stores
-                         // there the segment count of level L + 1 (0 after an error)
+  uint64_t* h_pace;      // pinned host words, or null: once level L's histogram pass has made
+                         // level L + 1's segments and level L's leaf jobs, its last workgroup
+                         // stores pace_word(token, that segment count (0 after an error),
+                         // whether there are leaf jobs) at [L + 1]
+  uint32_t pace_token;   // the call's token (24 bits), so that no store of an earlier call is taken
   uint32_t seg_cap, work_cap, leaf_cap, status_cap, tile_cap;
   uint32_t force_clear;  // 1: clear the scan rows in this call (set-up of a new layout)
   uint64_t status_words; // words of the scan-row region

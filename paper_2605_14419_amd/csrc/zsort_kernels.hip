@@ -540,6 +540,7 @@ __global__ void k_reset(Ws ws) {
   const int t = threadIdx.x;
   if (t < kMaxLevels) {
     c->tick[t] = 0;
+    c->hdone[t] = 0;
     c->lvl_keys[t] = 0;
     c->lvl_mkeys[t] = 0;
     c->lvl_fkeys[t] = 0;
@@ -1702,6 +1703,23 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
     if (sm.st_keys) atomicAdd((unsigned long long*)&c->lvl_keys[L], sm.st_keys);
     if (sm.st_segs) atomicAdd(&c->lvl_segs[L], sm.st_segs);
     if (sm.st_groups) atomicAdd(&c->n_leafgroups, sm.st_groups);
+    // the host paces the levels by the next level's segment count and
+    // whether this level has leaf jobs: the last workgroup to finish stores
+    // both straight into the host's pinned memory.  (Every list allocation of
+    // a workgroup returned before its barrier, so the counts read after this
+    // atomic are final.)
+    if (ws.h_pace && atomicAdd(&c->hdone[L], 1u) == gridDim.x - 1u) {
+      const int S = L & 1;
+      const uint32_t ns = __hip_atomic_load(&c->nseg[S ^ 1], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t nl = __hip_atomic_load(&c->nleaf[S], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                          __hip_atomic_load(&c->nleafw[S], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                          __hip_atomic_load(&c->nleafm[S], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                          __hip_atomic_load(&c->nleafx[S], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool failed = call_failed(c);
+      __hip_atomic_store(&ws.h_pace[L + 1], pace_word(ws.pace_token, failed ? 0u : ns, nl != 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -2677,11 +2695,6 @@ __global__ void __launch_bounds__(kBlock) k_local_hard(Ws ws, int L) {
   using Sm = LocSmem<PW>;
   __shared__ Sm sm;
   Ctl* c = ws.ctl;
-  // the host paces the levels by the next level's segment count, stored
-  // straight into its pinned memory (no copy in the stream)
-  if (ws.h_nseg && blockIdx.x == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&ws.h_nseg[L + 1], call_failed(c) ? 0u : c->nseg[(L + 1) & 1],
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (call_failed(c)) return;
   const int S = L & 1;
   const uint32_t nh = min(c->nhard[S], ws.leaf_cap);
