@@ -299,6 +299,9 @@ int zsort_set_alloc_limit(size_t max_bytes);
  *                     pass's subproblems come from that pass's scatter, and
  *                     their keys are not read again for them)
  *   local_keys        keys the local kernel sorted or copied into place
+ *   fallback_groups   leaf groups left to the fallback sort (key range above 51
+ *                     bits that the wide path could not take, or a bucket of
+ *                     more than 128 keys that is not a run of one key value)
  *   model_bytes       algorithmic HBM bytes of the executed pass structure:
  *                     8 B per key of a moments pass, 8 B per key of a
  *                     histogram pass, 2(8+P) B per key of a scatter pass and
@@ -320,7 +323,7 @@ typedef struct zsort_stats {
   uint64_t local_keys;
   double model_bytes;
   uint32_t counted;     /* subproblems finished by a counting pass (count_range) */
-  uint32_t reserved;
+  uint32_t fallback_groups;  /* leaf groups the local sorts left to the fallback sort */
 } zsort_stats;
 
 int zsort_get_last_stats(void* stream, zsort_stats* out /* host */);

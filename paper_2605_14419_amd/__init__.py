@@ -59,7 +59,7 @@ class ZsortStats(ctypes.Structure):
                 ("segs_per_level", ctypes.c_uint32 * MAX_LEVELS),
                 ("local_keys", ctypes.c_uint64),
                 ("model_bytes", ctypes.c_double),
-                ("counted", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("counted", ctypes.c_uint32), ("fallback_groups", ctypes.c_uint32)]
 
 
 class ZsortU128Report(ctypes.Structure):
@@ -307,7 +307,8 @@ def zsort_get_last_stats(stream=None) -> dict:
                 keys_per_level=list(s.keys_per_level[:L]),
                 mkeys_per_level=list(s.mkeys_per_level[:L]),
                 segs_per_level=list(s.segs_per_level[:L]), local_keys=s.local_keys,
-                model_bytes=s.model_bytes, counted=s.counted)
+                model_bytes=s.model_bytes, counted=s.counted,
+                fallback_groups=s.fallback_groups)
 
 
 def zsort_debug_level0(keys, payload=None, cfg=None, stream=None):

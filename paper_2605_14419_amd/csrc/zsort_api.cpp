@@ -1178,6 +1178,7 @@ int zsort_get_last_stats(void* stream, zsort_stats* out) {
   bytes += 2 * kp * (double)ctl.local_keys + w->last_extra_bytes;
   out->local_keys = ctl.local_keys;
   out->counted = ctl.n_count;
+  out->fallback_groups = ctl.n_hard;
   out->levels = levels;
   out->model_bytes = bytes;
   return ZSORT_OK;

@@ -137,6 +137,7 @@ struct __attribute__((aligned(64))) Ctl {
   uint32_t max_level;
   uint64_t local_keys;           // keys sorted or copied by the local kernel
   uint32_t n_count;              // subproblems finished by a counting pass
+  uint32_t n_hard;               // leaf groups left to the fallback sort
 };
 
 enum : uint32_t { ERR_SEGCAP = 1u, ERR_WORKCAP = 2u, ERR_LEAFCAP = 4u, ERR_STATUSCAP = 8u,

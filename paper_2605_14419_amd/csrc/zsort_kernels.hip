@@ -566,6 +566,7 @@ __global__ void k_reset(Ws ws) {
     c->ntrace_hist = 0;
     c->n_ident = c->n_rmap = c->n_leafgroups = 0;
     c->n_count = 0;
+    c->n_hard = 0;
     c->max_level = 0;
     c->local_keys = 0;
   }
@@ -2153,10 +2154,11 @@ __device__ __forceinline__ uint32_t c16_get(const uint32_t* c, uint32_t b) {
 
 // Turns the nb 16-bit bucket counters (two per word) into exclusive starts;
 // returns false, leaving the counters as they are, if some bucket holds more
-// than kBucketMax keys.  Each thread owns ceil(nb / TT) consecutive counters.
+// than kBucketMax keys (unless limit is false).  Each thread owns
+// ceil(nb / TT) consecutive counters.
 template <int TW>
 __device__ __forceinline__ bool bucket_starts(uint32_t* cnt, uint32_t nb, uint32_t* sh,
-                                              uint32_t tid) {
+                                              uint32_t tid, bool limit = true) {
   constexpr uint32_t TT = TW * kWave;
   const uint32_t tw = tid / kWave, ln = tid & (kWave - 1);
   const uint32_t per = (nb + TT - 1) / TT;
@@ -2171,7 +2173,7 @@ __device__ __forceinline__ bool bucket_starts(uint32_t* cnt, uint32_t nb, uint32
     }
   }
   uint32_t base;
-  uint32_t big = __ballot(tmax > (uint32_t)kBucketMax) != 0ull ? 1u : 0u;
+  uint32_t big = __ballot(limit && tmax > (uint32_t)kBucketMax) != 0ull ? 1u : 0u;
   if constexpr (TW == 1) {
     base = wave_incl_sum(tsum) - tsum;
   } else {
@@ -2634,25 +2636,83 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
     }
   }
   team_sync<TW>();
-  if (!bucket_starts<TW>(cnt, nb, sh, tid)) return false;
+  // a bucket above kBucketMax keys: a one-wave group takes it if every such
+  // bucket holds one key value (a run of duplicates, Section III's duplicate
+  // handling), placed in input order; otherwise the group is left to the
+  // fallback sort
+  bool runs = false;
+  if (!bucket_starts<TW>(cnt, nb, sh, tid)) {
+    if constexpr (TW != 1) return false;
+    runs = true;
+    bucket_starts<TW>(cnt, nb, sh, tid, false);
+  }
   // place the words
+  if (!runs) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = r * TT + tid;
-    if (i < n) {
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = r * TT + tid;
+      if (i < n) {
+        const uint64_t dlt = key[r] - mn;
+        const uint32_t b = (uint32_t)(dlt >> shb);
+        const uint32_t sft = (b & 1u) * 16u;
+        const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sft);
+        const uint32_t pos = min((old >> sft) & 0xFFFFu, (uint32_t)(TT * R) - 1);
+        kb[pos] = (dlt << 12) | i;
+      }
+    }
+  } else if constexpr (TW == 1) {
+    // stable placement: round by round (positions in order), the lanes of a
+    // bucket in lane order after the bucket's earlier rounds; the lowest lane
+    // of each bucket advances its counter for all of them
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = r * TT + tid;
+      const bool valid = i < n;
       const uint64_t dlt = key[r] - mn;
-      const uint32_t b = (uint32_t)(dlt >> shb);
+      const uint32_t b = valid ? (uint32_t)(dlt >> shb) : 0u;
+      uint64_t peers = __ballot(valid);
+      for (int q = 0; (1u << q) < nb; ++q) {
+        const bool bit = ((b >> q) & 1u) != 0;
+        const uint64_t m = __ballot(valid && bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t lead = valid ? (uint32_t)__ffsll((unsigned long long)peers) - 1u : 0u;
       const uint32_t sft = (b & 1u) * 16u;
-      const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sft);
-      const uint32_t pos = min((old >> sft) & 0xFFFFu, (uint32_t)(TT * R) - 1);
-      kb[pos] = (dlt << 12) | i;
+      uint32_t old = 0;
+      if (valid && tid == lead) old = atomicAdd(&cnt[b >> 1], (uint32_t)__popcll(peers) << sft);
+      old = __shfl(old, (int)lead);
+      if (valid) {
+        const uint32_t below = (uint32_t)__popcll(peers & ((1ull << tid) - 1ull));
+        const uint32_t pos = min(((old >> sft) & 0xFFFFu) + below, (uint32_t)(TT * R) - 1);
+        kb[pos] = (dlt << 12) | i;
+      }
     }
   }
   team_sync<TW>();
+  if (runs) {
+    // every bucket above kBucketMax keys must hold one key value
+    bool mixed = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = r * TT + tid;
+      if (i < n) {
+        const uint64_t v = kb[i];
+        const uint32_t b = (uint32_t)((v >> 12) >> shb);
+        const uint32_t e = c16_get(cnt, b);
+        const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
+        if (e - s0 > (uint32_t)kBucketMax && (v >> 12) != (kb[s0] >> 12)) mixed = true;
+      }
+    }
+    if (__ballot(mixed) != 0ull) {
+      team_sync<TW>();
+      return false;
+    }
+  }
   // Bucket b now spans [end(b-1), end(b)).  A word's place in the output is
   // its bucket's start plus the number of smaller words in the bucket (the
-  // words are unique).  Keys and payloads go straight to their places (a
-  // permutation inside each bucket: nearly sequential).
+  // words are unique); in a run of one key value, placed in input order, its
+  // slot.  Keys and payloads go straight to their places (a permutation
+  // inside each bucket: nearly sequential).
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t i = r * TT + tid;
@@ -2661,9 +2721,12 @@ __device__ bool fast_sort_regs(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t*
       const uint32_t b = (uint32_t)((v >> 12) >> shb);
       const uint32_t e = c16_get(cnt, b);
       const uint32_t s0 = b ? c16_get(cnt, b - 1) : 0u;
-      uint32_t rank = 0;
-      for (uint32_t j = s0; j < e; ++j) rank += kb[j] < v ? 1u : 0u;
-      const uint32_t p = min(s0 + rank, n - 1);
+      uint32_t p = i;
+      if (!runs || e - s0 <= (uint32_t)kBucketMax) {
+        uint32_t rank = 0;
+        for (uint32_t j = s0; j < e; ++j) rank += kb[j] < v ? 1u : 0u;
+        p = min(s0 + rank, n - 1);
+      }
       dst[start + p] = (v >> 12) + mn;
       if constexpr (PW != 0) pay_store<PW>(pdst, start + p, pb[v & 4095u]);
     }
@@ -2685,6 +2748,7 @@ __device__ bool fast_sort(uint64_t* kb, typename PayT<PW>::T* pb, uint32_t* cnt,
 }
 
 __device__ void push_hard(Ws& ws, int S, const Leaf& lf) {
+  atomicAdd(&ws.ctl->n_hard, 1u);
   const uint32_t h = atomicAdd(&ws.ctl->nhard[S], 1u);
   if (h < ws.leaf_cap) ws.hard[S][h] = lf;
   else atomicOr(&ws.ctl->error, ERR_LEAFCAP);
