@@ -1282,53 +1282,66 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
   zsort_config win;
   zsort_default_config(&win);
   float win_ms = 1e30f;
+  // the faster of two runs after a warm-up one (1e30: a device-side limit
+  // was hit, the candidate is out)
+  auto time_cfg = [&](const zsort_config& c) -> float {
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      e = hipMemcpyAsync(tk, keys, n * 8, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && payload_bytes)
+        e = hipMemcpyAsync(tp, payload, n * (size_t)payload_bytes, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e != hipSuccess) break;
+      Call call{tk, payload_bytes ? tp : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
+                num_segments, c, 0, 0, false};
+      Workspace* w = nullptr;
+      rc = run(call, st, &w);
+      if (rc) break;
+      e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      uint32_t derr = 0;
+      if (e == hipSuccess)
+        e = hipMemcpy(&derr, w->base + w->lay.off_ctl + offsetof(zs::Ctl, error), 4,
+                      hipMemcpyDeviceToHost);
+      if (derr) return 1e30f;
+      if (rep > 0 && ms < t_best) t_best = ms;  // first run warms up
+    }
+    return t_best;
+  };
   const int ks[3] = {256, 512, 1024};
   // (tile, chunk): one-tile work items put the runs of neighbouring tiles
   // side by side in memory at the same time; larger ones cost the histogram
   // pass less
   const int tiles[4][2] = {{2048, 16384}, {4096, 32768}, {8192, 8192}, {8192, 32768}};
   const int cuts[3] = {1024, 2048, 4096};
-  for (int a = 0; a < 3 && e == hipSuccess; ++a)
-    for (int b = 0; b < 4 && e == hipSuccess; ++b)
-      for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+  for (int a = 0; a < 3 && e == hipSuccess && !rc; ++a)
+    for (int b = 0; b < 4 && e == hipSuccess && !rc; ++b)
+      for (int d = 0; d < 3 && e == hipSuccess && !rc; ++d) {
         zsort_config c;
         zsort_default_config(&c);
         c.k = ks[a];
         c.tile = tiles[b][0];
         c.chunk = tiles[b][1];
         c.cutoff = cuts[d];
-        float t_best = 1e30f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-          e = hipMemcpyAsync(tk, keys, n * 8, hipMemcpyDeviceToDevice, st);
-          if (e == hipSuccess && payload_bytes)
-            e = hipMemcpyAsync(tp, payload, n * (size_t)payload_bytes, hipMemcpyDeviceToDevice, st);
-          if (e == hipSuccess) e = hipEventRecord(e0, st);
-          if (e != hipSuccess) break;
-          Call call{tk, payload_bytes ? tp : nullptr, payload_bytes, (uint64_t)n, seg_offsets,
-                    num_segments, c, 0, 0, false};
-          Workspace* w = nullptr;
-          rc = run(call, st, &w);
-          if (rc) break;
-          e = hipEventRecord(e1, st);
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          uint32_t derr = 0;   // a device-side limit: the candidate is out
-          if (e == hipSuccess)
-            e = hipMemcpy(&derr, w->base + w->lay.off_ctl + offsetof(zs::Ctl, error), 4,
-                          hipMemcpyDeviceToHost);
-          if (derr) {
-            t_best = 1e30f;
-            break;
-          }
-          if (rep > 0 && ms < t_best) t_best = ms;  // first run warms up
-        }
-        if (rc) break;
-        if (t_best < win_ms) {
-          win_ms = t_best;
+        const float t = time_cfg(c);
+        if (t < win_ms) {
+          win_ms = t;
           win = c;
         }
       }
+  // the winner with z-score maps on its first one or two levels only
+  for (int z = 1; z <= 2 && win_ms < 1e29f && e == hipSuccess && !rc; ++z) {
+    zsort_config c = win;
+    if (c.max_zlevels <= z) break;
+    c.max_zlevels = z;
+    const float t = time_cfg(c);
+    if (t < win_ms) {
+      win_ms = t;
+      win = c;
+    }
+  }
   // the winner once more: its output must be sorted (single arrays) before it
   // is remembered
   uint32_t unsorted = win_ms < 1e29f ? 0u : 1u;

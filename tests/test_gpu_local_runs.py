@@ -127,3 +127,24 @@ def test_duplicate_runs_in_one_wave_mid_groups_vs_oracle():
     ok, oi = oracle.sort_segmented(keys, off, idx, k=1024, cutoff=2048, max_zlevels=8)
     assert np.array_equal(tk.cpu().numpy().view(np.uint64), ok)
     assert np.array_equal(tp.cpu().numpy().view(np.uint32), oi)
+
+
+def test_duplicate_runs_in_largest_block_groups_vs_oracle():
+    """groups of 2049..4096 keys (cutoff 4096: a 512-thread workgroup each)
+    with runs of one value: these workgroup jobs leave every group with an
+    overfull bucket to the fallback sort (placing their words stably wave by
+    wave cost more than the fallback), which orders them like the oracle"""
+    cfg = dict(k=1024, cutoff=4096, max_zlevels=8, chunk=16384)
+    keys, off = build(53, ["run", "narrow", "small", "equal"], 2049, 4096, 60)
+    idx = np.arange(keys.size, dtype=np.uint32)
+    tk = torch.from_numpy(keys.view(np.int64)).to(DEV)
+    tp = torch.from_numpy(idx.view(np.int32)).to(DEV)
+    say(f"case block duplicate runs n={keys.size}")
+    zs.zsort_stable_segmented(tk, torch.from_numpy(off).to(DEV), tp, cfg)
+    torch.cuda.synchronize()
+    st = zs.zsort_get_last_stats()
+    assert st["device_error"] == 0, st
+    assert st["fallback_groups"] == 30, st   # the run and narrow groups
+    ok, oi = oracle.sort_segmented(keys, off, idx, k=1024, cutoff=4096, max_zlevels=8)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), ok)
+    assert np.array_equal(tp.cpu().numpy().view(np.uint32), oi)
