@@ -205,6 +205,12 @@ struct Workspace {
   uint32_t* h_nseg = nullptr;  // pinned, kMaxLevels + 1 words
   hipEvent_t lvl_ev[zs::kMaxLevels] = {};
   bool lvl_ev_ok = false;
+  // the local sorts of a level run on a second stream beside the next level:
+  // an event after each level's scatter (the local sorts wait for it) and
+  // after each level's local sorts (level L + 2 waits for those of level L)
+  hipStream_t side = nullptr;
+  hipEvent_t scat_ev[zs::kMaxLevels] = {};
+  hipEvent_t loc_ev[zs::kMaxLevels] = {};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_stage;  // stage of each (start, end) pair
@@ -461,9 +467,20 @@ bool pacing_ready(Workspace* w) {
     std::memset(p, 0, (zs::kMaxLevels + 1) * sizeof(uint64_t));
     w->h_pace = (uint64_t*)p;
   }
-  for (int i = 0; i < zs::kMaxLevels; ++i)
+  for (int i = 0; i < zs::kMaxLevels; ++i) {
     if (!w->lvl_ev[i] && hipEventCreateWithFlags(&w->lvl_ev[i], hipEventDisableTiming) != hipSuccess)
       return false;
+    if (!w->scat_ev[i] &&
+        hipEventCreateWithFlags(&w->scat_ev[i], hipEventDisableTiming | hipEventDisableSystemFence) !=
+            hipSuccess)
+      return false;
+    if (!w->loc_ev[i] &&
+        hipEventCreateWithFlags(&w->loc_ev[i], hipEventDisableTiming | hipEventDisableSystemFence) !=
+            hipSuccess)
+      return false;
+  }
+  if (!w->side && hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking) != hipSuccess)
+    return false;
   w->lvl_ev_ok = true;
   return true;
 }
@@ -625,12 +642,32 @@ hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t
     wsp.h_pace = w->h_pace;
     wsp.pace_token = token;
   }
-  auto locals = [&](int L) {
+  auto locals = [&](int L, hipStream_t ls) {
     hipError_t r = stage(w, wsp, L, zs::STAGE_LOCAL, grid_size(c.cfg.k, c.pw, c.cfg.tile,
-                                                               zs::STAGE_LOCAL), st);
+                                                               zs::STAGE_LOCAL), ls);
     if (r == hipSuccess)
       r = stage(w, wsp, L, zs::STAGE_LOCAL_HARD,
-                grid_size(c.cfg.k, c.pw, c.cfg.tile, zs::STAGE_LOCAL_HARD), st);
+                grid_size(c.cfg.k, c.pw, c.cfg.tile, zs::STAGE_LOCAL_HARD), ls);
+    return r;
+  };
+  // Paced, a level's local sorts run on the second stream once its scatter
+  // has ended, beside the next level's read passes (moments, statistics,
+  // histogram): they read only this level's leaf lists and leaf ranges, which
+  // those passes do not touch (the moments pass empties the lists of its own
+  // slot only).  The next level's scatter waits for them: beside it (one
+  // workgroup per compute unit, most of the LDS) they cost it more than they
+  // gain.  The caller's stream waits for the last of them.
+  bool on_side[zs::kMaxLevels] = {};
+  int last_side = -1;
+  auto side_locals = [&](int L) {
+    hipError_t r = hipEventRecord(w->scat_ev[L], st);
+    if (r == hipSuccess) r = hipStreamWaitEvent(w->side, w->scat_ev[L], 0);
+    if (r == hipSuccess) r = locals(L, w->side);
+    if (r == hipSuccess) r = hipEventRecord(w->loc_ev[L], w->side);
+    if (r == hipSuccess) {
+      on_side[L] = true;
+      last_side = L;
+    }
     return r;
   };
   int pending = -1;   // the level whose local sorts wait for its histogram pass's word
@@ -639,24 +676,34 @@ hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t
       uint32_t nseg = 0;
       bool leaves = true;
       e = wait_pace(w, ws, L, token, st, &nseg, &leaves);
-      if (e == hipSuccess && leaves) e = locals(pending);
+      // (with no level after it, nothing would run beside them)
+      if (e == hipSuccess && leaves) e = nseg ? side_locals(pending) : locals(pending, st);
       pending = -1;
       if (e != hipSuccess || nseg == 0) break;
     } else if (paced && L >= 2) {   // the learned form's hand-over
       e = hipEventSynchronize(w->lvl_ev[L - 2]);
       if (e != hipSuccess || w->h_nseg[L - 1] == 0) break;
     }
-    for (int sid = zs::STAGE_MOMENTS; sid <= zs::STAGE_SCATTER && e == hipSuccess; ++sid)
-      e = stage(w, wsp, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
+    for (int sid = zs::STAGE_MOMENTS; sid <= zs::STAGE_SCATTER && e == hipSuccess; ++sid) {
+      // the scatter (one workgroup per compute unit, most of the LDS) waits
+      // for the previous level's local sorts; the read passes run beside them
+      if (sid == zs::STAGE_SCATTER && L >= 1 && on_side[L - 1])
+        e = hipStreamWaitEvent(st, w->loc_ev[L - 1], 0);
+      if (e == hipSuccess) e = stage(w, wsp, L, sid, grid_size(c.cfg.k, c.pw, c.cfg.tile, sid), st);
+    }
     if (e != hipSuccess || c.level0_only) continue;
     if (paced) pending = L;
-    else e = locals(L);
+    else e = locals(L, st);
   }
   if (e == hipSuccess && pending >= 0) {   // the last level launched
     uint32_t nseg = 0;
     bool leaves = true;
     e = wait_pace(w, ws, pending + 1, token, st, &nseg, &leaves);
-    if (e == hipSuccess && leaves) e = locals(pending);
+    if (e == hipSuccess && leaves) e = locals(pending, st);
+  }
+  if (last_side >= 0) {
+    const hipError_t j = hipStreamWaitEvent(st, w->loc_ev[last_side], 0);
+    if (e == hipSuccess) e = j;
   }
   return e;
 }
@@ -1425,6 +1472,11 @@ int zsort_release(void) {
     for (hipEvent_t ev : w->ev_pool) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : w->lvl_ev)
       if (ev) (void)hipEventDestroy(ev);
+    for (int i = 0; i < zs::kMaxLevels; ++i) {
+      if (w->scat_ev[i]) (void)hipEventDestroy(w->scat_ev[i]);
+      if (w->loc_ev[i]) (void)hipEventDestroy(w->loc_ev[i]);
+    }
+    if (w->side) (void)hipStreamDestroy(w->side);
     if (w->h_nseg) (void)hipHostFree(w->h_nseg);
     if (w->h_pace) (void)hipHostFree(w->h_pace);
     delete w;

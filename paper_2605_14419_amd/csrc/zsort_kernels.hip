@@ -948,10 +948,16 @@ __global__ void __launch_bounds__(kBlock) k_moments(Ws ws, int L) {
   Ctl* c = ws.ctl;
   const int S = L & 1, N = S ^ 1;
   if (call_failed(c)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {  // lists of level L+1 start empty
-    c->nseg[N] = 0; c->nwork[N] = 0; c->nleaf[N] = 0; c->nleafw[N] = 0; c->nleafm[N] = 0;
-    c->nleafx[N] = 0; c->nhard[N] = 0;
-    c->nstatus[N] = 0; c->ntile[N] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the segment lists of level L + 1 start empty
+    c->nseg[N] = 0; c->nwork[N] = 0; c->nstatus[N] = 0; c->ntile[N] = 0;
+    // and so do this level's leaf lists (level 0's may already hold the
+    // set-up's jobs).  They are emptied here rather than a level earlier, so
+    // that the local sorts of level L - 2, which read this slot's lists, may
+    // still be running beside level L - 1.
+    if (L >= 1) {
+      c->nleaf[S] = 0; c->nleafw[S] = 0; c->nleafm[S] = 0; c->nleafx[S] = 0; c->nhard[S] = 0;
+    }
   }
   const uint32_t nw = min(c->nwork[S], ws.work_cap);
   const uint64_t* __restrict__ x = ws.keys[S];
