@@ -565,7 +565,8 @@ int run(const Call& c, hipStream_t st, Workspace** wout) {
   return ZSORT_OK;
 }
 
-hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0);
+hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0,
+                          bool beside = true);
 
 // the launch sequence of one sort on stream st (signed keys: the sign bit
 // is flipped before and after, so that the unsigned sort orders them)
@@ -621,8 +622,10 @@ hipError_t wait_pace(Workspace* w, const Ws& ws, int L, uint32_t token, hipStrea
 }
 
 // levels L0, L0 + 1, ... (L0 > 0: level L0 - 1 ran already; with L0 >= 2
-// its segment count was copied to h_nseg[L0 - 1] before event lvl_ev[L0 - 2])
-hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0) {
+// its segment count was copied to h_nseg[L0 - 1] before event lvl_ev[L0 - 2]);
+// beside: local sorts may run beside the next level (below)
+hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t st, int L0,
+                          bool beside) {
   hipError_t e = hipSuccess;
   const int levels = c.level0_only ? 1 : levels_for(c.cfg);
   // Pacing: once level L's histogram pass ends, its last workgroup stores
@@ -677,7 +680,7 @@ hipError_t enqueue_levels(Workspace* w, const Ws& ws, const Call& c, hipStream_t
       bool leaves = true;
       e = wait_pace(w, ws, L, token, st, &nseg, &leaves);
       // (with no level after it, nothing would run beside them)
-      if (e == hipSuccess && leaves) e = nseg ? side_locals(pending) : locals(pending, st);
+      if (e == hipSuccess && leaves) e = nseg && beside ? side_locals(pending) : locals(pending, st);
       pending = -1;
       if (e != hipSuccess || nseg == 0) break;
     } else if (paced && L >= 2) {   // the learned form's hand-over
@@ -1728,9 +1731,9 @@ int zsort_stable_learned(uint64_t* keys, void* payload, int payload_bytes, size_
         e = hipMemcpyAsync(&w->h_nseg[2], &ws.ctl->nseg[0], sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipEventRecord(w->lvl_ev[1], st);
-      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 2);
+      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 2, false);
     } else {
-      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 1);
+      if (e == hipSuccess) e = enqueue_levels(w, wz, cz, st, 1, false);
     }
   }
   if (e != hipSuccess) return hip_fail(e);
