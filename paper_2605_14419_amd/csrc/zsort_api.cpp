@@ -1465,6 +1465,11 @@ int zsort_profile_end(void* stream, zsort_kernel_times* out) {
 int zsort_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = ZSORT_OK;
+  // (work may still run on the library's own streams: the local sorts' stream)
+  if (!g_ws.empty() || !g_ws_aux.empty()) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
   auto free_ws = [&](Workspace* w) {
     drop_graphs(w);
     if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);

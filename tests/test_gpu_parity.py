@@ -475,3 +475,21 @@ def test_wide_range_leaves_after_a_pass_vs_oracle(k, pw, name):
     assert np.array_equal(kk, ok)
     if pw:
         assert np.array_equal(p, op)
+
+
+def test_release_then_sort_again():
+    """zsort_release waits for the library's streams, frees its workspaces
+    and drops its graphs; the next calls lay everything out anew and sort
+    like the oracle (plain, with the local sorts beside the next level, and
+    through a captured graph)"""
+    x, idx = synth.make("lognormal", 300_007, payload_bytes=4)
+    cfg = dict(k=256, cutoff=1024, max_zlevels=8, chunk=32768, tile=8192)
+    ok, oi, _ = oracle.sort(x, idx, k=256, cutoff=1024, max_zlevels=8)
+    for rep in range(2):
+        say(f"case release then sort {rep}")
+        k, p, st = gpu_sort(x, idx, cfg)
+        assert st["device_error"] == 0, st
+        assert np.array_equal(k, ok) and np.array_equal(p, oi)
+        k, p, st = gpu_sort(x, idx, dict(cfg, flags=zs.ZSORT_FLAG_GRAPH))
+        assert np.array_equal(k, ok) and np.array_equal(p, oi)
+        zs.zsort_release()
