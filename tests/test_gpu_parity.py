@@ -493,3 +493,25 @@ def test_release_then_sort_again():
         k, p, st = gpu_sort(x, idx, dict(cfg, flags=zs.ZSORT_FLAG_GRAPH))
         assert np.array_equal(k, ok) and np.array_equal(p, oi)
         zs.zsort_release()
+
+
+def test_results_ordered_on_the_callers_stream():
+    """The local sorts of a level may run on the library's second stream; the
+    caller's stream waits for them. Work queued on the caller's (non-default)
+    stream right after the call, with no synchronisation in between, sees
+    the finished sort: a copy made there equals the oracle's output."""
+    x, idx = synth.make("lognormal", 2_000_003, payload_bytes=4)
+    cfg = dict(k=256, cutoff=4096, max_zlevels=8, chunk=32768, tile=8192)
+    ok, oi, _ = oracle.sort(x, idx, k=256, cutoff=4096, max_zlevels=8)
+    s = torch.cuda.Stream()
+    tk, tp = to_dev(x, idx)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            say(f"case caller stream {rep}")
+            ck, cp = tk.clone(), tp.clone()
+            zs.zsort_stable_ex(ck, cp, cfg, stream=s)
+            snap_k, snap_p = ck.clone(), cp.clone()   # queued on s right behind the sort
+            s.synchronize()
+            assert np.array_equal(snap_k.cpu().numpy().view(np.uint64), ok)
+            assert np.array_equal(snap_p.cpu().numpy().view(np.uint32), oi)
