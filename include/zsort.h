@@ -90,9 +90,13 @@ enum {
  *                levels exit at once).  The graph is captured on a private
  *                stream at the first call with a given set of buffers, shape
  *                and configuration, and replayed on `stream` afterwards.
- *                Without the flag the library launches level by level and
- *                stops one level after the recursion ends, waiting on the
- *                device's progress between levels (host-side pacing).
+ *                Without the flag the library launches level by level,
+ *                waiting for each level's histogram pass to learn whether
+ *                the level has local sorts and whether another level follows
+ *                (host-side pacing; the call returns once the last level is
+ *                known).  A level's local sorts may run on a second stream of
+ *                the library's beside the next level; `stream` waits for
+ *                them, so work queued on it after the call sees the result.
  *                ZSORT_FLAG_SIGNED: the keys are two's-complement int64 and
  *                are ordered as signed numbers (the sign bit is flipped in
  *                place before the sort and back after it: two more passes
