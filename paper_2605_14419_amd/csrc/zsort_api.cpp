@@ -460,9 +460,12 @@ bool pacing_ready(Workspace* w) {
     w->h_nseg = (uint32_t*)p;
   }
   if (!w->h_pace) {
+    // coherent (fine-grained) memory: the device's stores reach it while the
+    // kernels still run, and the host polls it
     void* p = nullptr;
-    if (hipHostMalloc(&p, (zs::kMaxLevels + 1) * sizeof(uint64_t), hipHostMallocDefault) !=
-        hipSuccess)
+    const size_t bytes = (zs::kMaxLevels + 1) * sizeof(uint64_t);
+    if (hipHostMalloc(&p, bytes, hipHostMallocCoherent) != hipSuccess &&
+        hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess)
       return false;
     std::memset(p, 0, (zs::kMaxLevels + 1) * sizeof(uint64_t));
     w->h_pace = (uint64_t*)p;
