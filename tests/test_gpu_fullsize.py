@@ -138,3 +138,22 @@ def test_u128_1e8_invariants_on_device(name):
     check_stable_sorted128_device(base_k.view(-1, 2), tk.view(-1, 2), tp)
     del base_k, tk, tp
     torch.cuda.empty_cache()
+
+
+def test_fused_statistics_1e8_invariants_on_device():
+    """The fused child statistics (opt-in) at 10^8 lognormal keys with a u64
+    index in the benchmark's configuration: sorted, a permutation carrying its
+    key, stable, and no moments pass below level 0."""
+    n = 10**8
+    keys, idx = synth.make("lognormal", n, payload_bytes=8)
+    base_k, base_p = dev(keys, idx)
+    del keys, idx
+    cfg = dict(bench.TUNED["lognormal"], flags=zs.ZSORT_FLAG_FUSED_STATS)
+    say(f"case fused 1e8 cfg={cfg}")
+    tk, tp = base_k.clone(), base_p.clone()
+    zs.zsort_stable_ex(tk, tp, cfg)
+    torch.cuda.synchronize()
+    st = zs.zsort_get_last_stats()
+    assert st["device_error"] == 0, st
+    assert st["levels"] >= 2 and sum(st["mkeys_per_level"][1:]) == 0, st["mkeys_per_level"]
+    check_stable_sorted_device(base_k, tk, tp)
