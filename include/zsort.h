@@ -145,7 +145,7 @@ int zsort_default_config(zsort_config* cfg);
  * Section III's choice of k and its table of alpha values): times candidate
  * configurations (k in {256, 512, 1024}; (tile, chunk) in {(2048, 16384),
  * (4096, 32768), (8192, 8192), (8192, 32768)}; cutoff in {1024, 2048, 4096}),
- * then the fastest of them with max_zlevels 1 and 2 as well (z-score maps on
+ * then the three fastest of them with max_zlevels 1 and 2 as well (z-score maps on
  * the first one or two levels, range maps below; a mixture of clusters sorts
  * in fewer levels so) on a scratch copy of keys/payload (device buffers, left unchanged;
  * seg_offsets may be NULL for a single array) and remembers the fastest that

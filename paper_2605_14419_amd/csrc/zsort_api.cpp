@@ -1335,6 +1335,10 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
   zsort_config win;
   zsort_default_config(&win);
   float win_ms = 1e30f;
+  constexpr int kTop = 3;
+  zsort_config top[kTop];
+  float top_ms[kTop] = {1e30f, 1e30f, 1e30f};
+  for (zsort_config& q : top) zsort_default_config(&q);
   // the faster of two runs after a warm-up one (1e30: a device-side limit
   // was hit, the candidate is out)
   auto time_cfg = [&](const zsort_config& c) -> float {
@@ -1379,22 +1383,33 @@ int zsort_autotune(const uint64_t* keys, const void* payload, int payload_bytes,
         c.chunk = tiles[b][1];
         c.cutoff = cuts[d];
         const float t = time_cfg(c);
-        if (t < win_ms) {
-          win_ms = t;
-          win = c;
+        // the three fastest so far, fastest first
+        int at = kTop;
+        while (at > 0 && t < top_ms[at - 1]) --at;
+        if (at < kTop) {
+          for (int q = kTop - 1; q > at; --q) {
+            top_ms[q] = top_ms[q - 1];
+            top[q] = top[q - 1];
+          }
+          top_ms[at] = t;
+          top[at] = c;
         }
       }
-  // the winner with z-score maps on its first one or two levels only
-  for (int z = 1; z <= 2 && win_ms < 1e29f && e == hipSuccess && !rc; ++z) {
-    zsort_config c = win;
-    if (c.max_zlevels <= z) break;
-    c.max_zlevels = z;
-    const float t = time_cfg(c);
-    if (t < win_ms) {
-      win_ms = t;
-      win = c;
+  win_ms = top_ms[0];
+  win = top[0];
+  // the three fastest with z-score maps on their first one or two levels
+  // only (another k or cutoff may win once the later levels take range maps)
+  for (int q = 0; q < kTop && top_ms[q] < 1e29f && e == hipSuccess && !rc; ++q)
+    for (int z = 1; z <= 2 && e == hipSuccess && !rc; ++z) {
+      zsort_config c = top[q];
+      if (c.max_zlevels <= z) break;
+      c.max_zlevels = z;
+      const float t = time_cfg(c);
+      if (t < win_ms) {
+        win_ms = t;
+        win = c;
+      }
     }
-  }
   // the winner once more: its output must be sorted (single arrays) before it
   // is remembered
   uint32_t unsorted = win_ms < 1e29f ? 0u : 1u;

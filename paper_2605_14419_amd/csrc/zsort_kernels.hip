@@ -1561,13 +1561,17 @@ __global__ void __launch_bounds__(kBlock) k_hist(Ws ws, int L) {
   }
 
   // items by ticket (the last arrivals at a scan unit or segment do more
-  // work, so a fixed share per workgroup would be uneven)
+  // work, so a fixed share per workgroup would be uneven), last item first:
+  // the moments pass reads the items in order and the scatter takes them in
+  // order, so each starts on keys the pass before it read last, some of which
+  // are still in the memory-side cache
   while (true) {
     if (t == 0) sm.w = atomicAdd(&c->tick[L], 1u);
     __syncthreads();
-    const uint32_t w = sm.w;
+    const uint32_t tk = sm.w;
     __syncthreads();
-    if (w >= nw) break;
+    if (tk >= nw) break;
+    const uint32_t w = nw - 1u - tk;
     const uint64_t item = ws.work[S][w];
     const uint32_t si = (uint32_t)(item >> 32), ci = (uint32_t)item;
     Seg& sg = ws.segs[S][si];
